@@ -1,0 +1,459 @@
+/*
+ * CPU oracle of the Cascade-of-Gaussians (CoG) background subtractor,
+ * arXiv 1705.09339.  TEST INFRASTRUCTURE ONLY (see cog_oracle.h): plain,
+ * slow and scalar on purpose, one pixel at a time, in the order the paper's
+ * steps are stated.  Build: gcc -O2 -std=c11 -ffp-contract=off (no fast-math).
+ *
+ * Where the paper is silent or garbled the oracle takes the readings that the
+ * design notes list (KDE form, GMM initialisation, rho, sigma^2 update, match
+ * rule, sort key, confidence terms, learning-rate function).  Each function
+ * below names the passage it follows.
+ */
+#include "cog_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NBINS 16
+#define NLEVELS 256
+
+struct orc_state {
+  orc_params p;
+  int64_t npix;
+  int32_t n_train;  /* 0 until trained */
+  int64_t frame;    /* frames consumed so far */
+  float *gmm;       /* [npix][K][C+2]: w, mu[C], var -- rank order */
+  float *rga;       /* [npix][C+1]: mu_r[C], var_r */
+  uint8_t *table;   /* [npix][C][16] */
+  uint16_t *cnt;    /* [npix][3] */
+  uint8_t *label;   /* [npix] previous label */
+  float *prev;      /* [npix][C] previous frame value */
+  uint16_t W[NBINS][NLEVELS];
+};
+
+/* ---- scene-prior kernel weights (§2 "Scene Prior"; the KDE itself is not
+ * printed in the paper: per-channel Gaussian Parzen window of bandwidth h,
+ * integrated over 16 bins of 16 levels, integer weights summing to ~65535).
+ * W[b][v] = rint(65535 * sum_{u=16b}^{16b+15} phi(u-v)),
+ * phi(d) = exp(-d^2/(2h^2)) / sum_{e=-1024}^{1024} exp(-e^2/(2h^2)).
+ * Mass that falls outside [0,255] is dropped. */
+int orc_kde_weights(double h, uint16_t *out) {
+  if (!(h > 0.0) || !out) return -1;
+  const double den = 2.0 * h * h;
+  double z = 0.0;
+  for (int e = -1024; e <= 1024; ++e) z += exp(-(double)(e * e) / den);
+  for (int b = 0; b < NBINS; ++b) {
+    for (int v = 0; v < NLEVELS; ++v) {
+      double s = 0.0;
+      for (int u = NBINS * b; u < NBINS * b + NBINS; ++u) {
+        int d = u - v;
+        s += exp(-(double)(d * d) / den) / z;
+      }
+      out[b * NLEVELS + v] = (uint16_t)rint(65535.0 * s);
+    }
+  }
+  return 0;
+}
+
+/* ---- helpers ------------------------------------------------------------- */
+
+static float load_x(const orc_params *p, const void *frame, int64_t pix, int c) {
+  if (p->dtype == ORC_U8) return (float)((const uint8_t *)frame)[pix * p->channels + c];
+  return ((const float *)frame)[pix * p->channels + c];
+}
+
+/* Prior quantization q(v): u8 levels directly; f32 values mapped linearly
+ * from [in_lo, in_hi) onto 256 levels (latent-space input, §3.3). */
+static int quant(const orc_params *p, float v) {
+  if (p->dtype == ORC_U8) return (int)v;
+  float s = 256.0f / (p->in_hi - p->in_lo);
+  float q = floorf((v - p->in_lo) * s);
+  if (q < 0.0f) return 0;
+  if (q > 255.0f) return 255;
+  return (int)q;
+}
+
+/* delta = max_c |x_c - x'_c| (frame difference, §2 "Confidence Measure"). */
+static float frame_delta(int C, const float *x, const float *xp) {
+  float dl = 0.0f;
+  for (int c = 0; c < C; ++c) {
+    float d = x[c] - xp[c];
+    if (d < 0.0f) d = -d;
+    if (d > dl) dl = d;
+  }
+  return dl;
+}
+
+static float fmax0(float lo, float v) { return v < lo ? lo : v; }
+
+/* ---- Stauffer-Grimson mixture step (§2, the update equation under "Scene
+ * Prior": w <- (1-a)w + a M, mu <- (1-rho)mu + rho I, sigma^2 likewise with
+ * the squared residual; diagonal -- here isotropic -- covariance). ---------- */
+
+/* Background set: the smallest b with cumulative weight > T (else K). */
+int orc_pixel_bgset(const orc_params *p, const float *comp) {
+  const int F = p->channels + 2;
+  float cum = 0.0f;
+  for (int b = 0; b < p->K; ++b) {
+    cum = cum + comp[b * F];
+    if (cum > p->T) return b + 1;
+  }
+  return p->K;
+}
+
+/* Slot a ranks before slot b iff w_a/sigma_a > w_b/sigma_b, compared without
+ * a square root as (w_a^2) sigma_b^2 > (w_b^2) sigma_a^2. */
+static int ranks_before(const float *a, const float *b, int C) {
+  float lhs = (a[0] * a[0]) * b[C + 1];
+  float rhs = (b[0] * b[0]) * a[C + 1];
+  return lhs > rhs;
+}
+
+int orc_pixel_gmmstep(const orc_params *p, float *comp, const float *x, float ae,
+                      int *label, int *m_post) {
+  const int K = p->K, C = p->channels, F = C + 2;
+  const float lam2 = p->lambda * p->lambda;
+
+  /* classify with the ranks and background set before the update */
+  const int B = orc_pixel_bgset(p, comp);
+  int m = -1;
+  for (int k = 0; k < K; ++k) {
+    const float *ck = comp + k * F;
+    if (!(ck[0] > 0.0f)) continue;
+    float d2 = 0.0f;
+    for (int c = 0; c < C; ++c) {
+      float d = x[c] - ck[1 + c];
+      d2 = d2 + d * d;
+    }
+    if (d2 <= lam2 * ck[1 + C]) {
+      m = k;
+      break;
+    }
+  }
+  const int lab = (m >= 0 && m < B) ? ORC_BG : ORC_FG;
+
+  /* weights: w_k <- (1-a) w_k + a M_k */
+  const float om = 1.0f - ae;
+  for (int k = 0; k < K; ++k) comp[k * F] = om * comp[k * F];
+  if (m >= 0) {
+    float *cm = comp + m * F;
+    cm[0] = cm[0] + ae;
+    /* matched component: rho = a / w_m, then the mean and variance moves */
+    const float rho = ae / cm[0];
+    const float orho = 1.0f - rho;
+    for (int c = 0; c < C; ++c) cm[1 + c] = orho * cm[1 + c] + rho * x[c];
+    float s = 0.0f;
+    for (int c = 0; c < C; ++c) {
+      float e = x[c] - cm[1 + c];
+      s = s + e * e;
+    }
+    cm[1 + C] = fmax0(p->var_min, orho * cm[1 + C] + rho * s);
+  } else {
+    /* no match: the least probable slot becomes a new component at x */
+    float *cl = comp + (K - 1) * F;
+    cl[0] = ae;
+    for (int c = 0; c < C; ++c) cl[1 + c] = x[c];
+    cl[1 + C] = p->var_init;
+  }
+
+  /* renormalise */
+  float S = 0.0f;
+  for (int k = 0; k < K; ++k) S = S + comp[k * F];
+  for (int k = 0; k < K; ++k) comp[k * F] = comp[k * F] / S;
+
+  /* stable insertion sort by w/sigma, following the matched slot */
+  int mp = m;
+  float tmp[2 + 8];
+  for (int i = 1; i < K; ++i) {
+    for (int j = i; j > 0 && ranks_before(comp + j * F, comp + (j - 1) * F, C); --j) {
+      memcpy(tmp, comp + j * F, sizeof(float) * F);
+      memcpy(comp + j * F, comp + (j - 1) * F, sizeof(float) * F);
+      memcpy(comp + (j - 1) * F, tmp, sizeof(float) * F);
+      if (mp == j) mp = j - 1;
+      else if (mp == j - 1) mp = j;
+    }
+  }
+  if (label) *label = lab;
+  if (m_post) *m_post = mp;
+  return 0;
+}
+
+/* ---- state ---------------------------------------------------------------- */
+
+static int params_ok(const orc_params *p) {
+  if (!p) return 0;
+  if (p->width <= 0 || p->height <= 0) return 0;
+  if (p->channels != 1 && p->channels != 3) return 0;
+  if (p->K < 1 || p->K > 8) return 0;
+  if (p->dtype != ORC_U8 && p->dtype != ORC_F32) return 0;
+  if (p->dtype == ORC_F32 && !(p->in_hi > p->in_lo)) return 0;
+  if (!(p->var_min > 0.0f) || !(p->var_init >= p->var_min)) return 0;
+  if (!(p->kde_h > 0.0f)) return 0;
+  if (!(p->res_e2 > 0.0f) || !(p->res_e1 <= p->res_e2)) return 0;
+  if (!(p->lambda_m > 0.0f)) return 0;
+  return 1;
+}
+
+orc_state *orc_create(const orc_params *p) {
+  if (!params_ok(p)) return NULL;
+  orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
+  if (!s) return NULL;
+  s->p = *p;
+  s->npix = (int64_t)p->width * p->height;
+  const int64_t P = s->npix;
+  const int C = p->channels, K = p->K;
+  s->gmm = (float *)calloc((size_t)(P * K * (C + 2)), sizeof(float));
+  s->rga = (float *)calloc((size_t)(P * (C + 1)), sizeof(float));
+  s->table = (uint8_t *)calloc((size_t)(P * C * NBINS), 1);
+  s->cnt = (uint16_t *)calloc((size_t)(P * 3), sizeof(uint16_t));
+  s->label = (uint8_t *)calloc((size_t)P, 1);
+  s->prev = (float *)calloc((size_t)(P * C), sizeof(float));
+  if (!s->gmm || !s->rga || !s->table || !s->cnt || !s->label || !s->prev ||
+      orc_kde_weights((double)p->kde_h, &s->W[0][0]) != 0) {
+    orc_destroy(s);
+    return NULL;
+  }
+  return s;
+}
+
+void orc_destroy(orc_state *s) {
+  if (!s) return;
+  free(s->gmm);
+  free(s->rga);
+  free(s->table);
+  free(s->cnt);
+  free(s->label);
+  free(s->prev);
+  free(s);
+}
+
+/* ---- training phase (§2 "Scene Prior", "Determining Learning Rate
+ * Hyper-parameters"): per pixel over the N training frames, the integer KDE
+ * bin masses, the 3-bin histogram of the frame-to-frame residue
+ * (static/drift, oscillating, dynamic), and a plain mixture warm-up. ------- */
+int orc_train(orc_state *s, const void *frames, int n) {
+  if (!s || !frames || n < 2 || n > 65536 || s->n_train != 0) return -1;
+  const orc_params *p = &s->p;
+  const int C = p->channels, K = p->K, F = C + 2;
+  const int64_t P = s->npix;
+  const size_t fstride = (size_t)P * C * (p->dtype == ORC_U8 ? 1 : 4);
+  const char *base = (const char *)frames;
+
+  for (int64_t px = 0; px < P; ++px) {
+    uint32_t acc[3][NBINS];
+    uint32_t cnt[3] = {0, 0, 0};
+    memset(acc, 0, sizeof(acc));
+    float *comp = s->gmm + px * K * F;
+    float x[3], xp[3];
+    int lab = ORC_BG;
+
+    /* mixture initialisation from the first frame: one component with a
+     * high initial variance, the others inactive */
+    for (int c = 0; c < C; ++c) x[c] = load_x(p, base, px, c);
+    for (int k = 0; k < K; ++k) {
+      comp[k * F] = (k == 0) ? 1.0f : 0.0f;
+      for (int c = 0; c < C; ++c) comp[k * F + 1 + c] = (k == 0) ? x[c] : 0.0f;
+      comp[k * F + 1 + C] = p->var_init;
+    }
+
+    for (int j = 0; j < n; ++j) {
+      const void *fr = base + (size_t)j * fstride;
+      for (int c = 0; c < C; ++c) x[c] = load_x(p, fr, px, c);
+      for (int c = 0; c < C; ++c) {
+        int q = quant(p, x[c]);
+        for (int b = 0; b < NBINS; ++b) acc[c][b] += s->W[b][q];
+      }
+      if (j >= 1) {
+        float dl = frame_delta(C, x, xp);
+        int bin = dl < p->res_e1 ? 0 : (dl < p->res_e2 ? 1 : 2);
+        cnt[bin] += 1;
+        orc_pixel_gmmstep(p, comp, x, p->alpha, &lab, NULL);
+      }
+      for (int c = 0; c < C; ++c) xp[c] = x[c];
+    }
+
+    /* max-normalised u8 table, exact integer rounding */
+    for (int c = 0; c < C; ++c) {
+      uint32_t amax = 0;
+      for (int b = 0; b < NBINS; ++b)
+        if (acc[c][b] > amax) amax = acc[c][b];
+      for (int b = 0; b < NBINS; ++b) {
+        uint64_t t = amax ? ((uint64_t)255 * acc[c][b] + amax / 2) / amax : 0;
+        s->table[(px * C + c) * NBINS + b] = (uint8_t)t;
+      }
+    }
+    for (int i = 0; i < 3; ++i) s->cnt[px * 3 + i] = (uint16_t)cnt[i];
+
+    /* running average seeded from the dominant mode; CHP state from frame N-1 */
+    for (int c = 0; c < C; ++c) s->rga[px * (C + 1) + c] = comp[1 + c];
+    s->rga[px * (C + 1) + C] = comp[1 + C];
+    s->label[px] = (uint8_t)lab;
+    for (int c = 0; c < C; ++c) s->prev[px * C + c] = xp[c];
+  }
+  s->n_train = n;
+  s->frame = n;
+  return 0;
+}
+
+/* ---- one frame of the rejection cascade (§2 "Cascade of Gaussians CoG",
+ * "Confidence Measure"): CHP, running Gaussian average, scene-prior
+ * confidence, then the full mixture; only the deciding level adapts. ------- */
+int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
+  if (!s || !frame || s->n_train == 0) return -1;
+  const orc_params *p = &s->p;
+  const int C = p->channels, K = p->K, F = C + 2;
+  const int64_t P = s->npix;
+  const float lam_r2 = p->lambda_rga * p->lambda_rga;
+  const float lam_m2 = p->lambda_m * p->lambda_m;
+  const float oar = 1.0f - p->alpha_rga;
+  const float pden = (C == 3) ? 16581375.0f : 255.0f;  /* 255^C */
+  const float nm1 = (float)(s->n_train - 1);
+  int64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, n3bg = 0, nfg = 0;
+
+  for (int64_t px = 0; px < P; ++px) {
+    float x[3];
+    for (int c = 0; c < C; ++c) x[c] = load_x(p, frame, px, c);
+    float *xp = s->prev + px * C;
+    float *rg = s->rga + px * (C + 1);
+    float *comp = s->gmm + px * K * F;
+    int lab;
+
+    /* S0: consistent hypothesis propagation (frame differencing) */
+    const float dl = frame_delta(C, x, xp);
+    if ((p->stage_mask & ORC_FD) && dl <= p->tau_fd) {
+      lab = s->label[px];
+      n0++;
+      goto done;
+    }
+    /* S1: running Gaussian average */
+    float dr2 = 0.0f;
+    for (int c = 0; c < C; ++c) {
+      float d = x[c] - rg[c];
+      dr2 = dr2 + d * d;
+    }
+    if ((p->stage_mask & ORC_RGA) && dr2 <= lam_r2 * rg[C]) {
+      lab = ORC_BG;
+      for (int c = 0; c < C; ++c) rg[c] = oar * rg[c] + p->alpha_rga * x[c];
+      float sr = 0.0f;
+      for (int c = 0; c < C; ++c) {
+        float e = x[c] - rg[c];
+        sr = sr + e * e;
+      }
+      rg[C] = fmax0(p->var_min, oar * rg[C] + p->alpha_rga * sr);
+      n1++;
+      goto done;
+    }
+    /* S2: scene prior lookup and confidence C = aP + bD + gM */
+    float conf = 0.0f;
+    if (p->stage_mask & ORC_KDE) {
+      const uint8_t *tb = s->table + px * C * NBINS;
+      uint32_t prod = 1;
+      for (int c = 0; c < C; ++c) prod = prod * tb[c * NBINS + (quant(p, x[c]) >> 4)];
+      const float ph = (float)prod / pden;
+      const uint16_t *ct = s->cnt + px * 3;
+      float a = (float)ct[0] / nm1;
+      const float b = (float)ct[1] / nm1;
+      const float g = (float)ct[2] / nm1;
+      if (ph < p->p_null) a = 0.0f; /* prior nullified */
+      const float dh = fmax0(0.0f, 1.0f - dl / p->res_e2);
+      const float mh = fmax0(0.0f, 1.0f - dr2 / (lam_m2 * rg[C]));
+      conf = (a * ph + b * dh) + g * mh;
+      if (conf >= p->conf_thr) {
+        lab = ORC_BG;
+        n2++;
+        goto done;
+      }
+    }
+    /* S3: full mixture with the confidence-driven learning rate */
+    {
+      const float ae = p->alpha * (1.0f - p->kappa_alpha * conf);
+      int mp = -1;
+      orc_pixel_gmmstep(p, comp, x, ae, &lab, &mp);
+      n3++;
+      if (lab == ORC_BG) {
+        n3bg++;
+        for (int c = 0; c < C; ++c) rg[c] = comp[mp * F + 1 + c];
+        rg[C] = comp[mp * F + 1 + C];
+      }
+    }
+  done:
+    if (lab == ORC_FG) nfg++;
+    if (mask) mask[px] = lab == ORC_FG ? 255 : 0;
+    s->label[px] = (uint8_t)lab;
+    for (int c = 0; c < C; ++c) xp[c] = x[c];
+  }
+  if (info) {
+    info[0] = s->frame;
+    info[1] = n0;
+    info[2] = n1;
+    info[3] = n2;
+    info[4] = n3;
+    info[5] = n3bg;
+    info[6] = nfg;
+    info[7] = ((double)n3 > (double)p->illum_frac * (double)P) ? 1 : 0;
+  }
+  s->frame++;
+  return 0;
+}
+
+/* ---- plain Stauffer-Grimson baseline (initialised on frame 0 by the training
+ * warm-up, then one mixture step per frame with the fixed rate alpha) ------- */
+int orc_gmm_step(orc_state *s, const void *frame, uint8_t *mask) {
+  if (!s || !frame || s->n_train == 0) return -1;
+  const orc_params *p = &s->p;
+  const int C = p->channels, K = p->K, F = C + 2;
+  for (int64_t px = 0; px < s->npix; ++px) {
+    float x[3];
+    int lab;
+    for (int c = 0; c < C; ++c) x[c] = load_x(p, frame, px, c);
+    orc_pixel_gmmstep(p, s->gmm + px * K * F, x, p->alpha, &lab, NULL);
+    if (mask) mask[px] = lab == ORC_FG ? 255 : 0;
+    s->label[px] = (uint8_t)lab;
+    for (int c = 0; c < C; ++c) s->prev[px * C + c] = x[c];
+  }
+  s->frame++;
+  return 0;
+}
+
+/* ---- canonical export: 64-byte header, then sections each padded to 64 B:
+ * gmm f32[P][K][C+2], rga f32[P][C+1], table u8[P][C][16], cnt u16[P][3],
+ * label u8[P], prev f32[P][C]. ---------------------------------------------- */
+static size_t pad64(size_t n) { return (n + 63) & ~(size_t)63; }
+
+size_t orc_canonical_bytes(const orc_params *p) {
+  if (!params_ok(p)) return 0;
+  const size_t P = (size_t)p->width * p->height;
+  const size_t C = (size_t)p->channels, K = (size_t)p->K;
+  return 64 + pad64(P * K * (C + 2) * 4) + pad64(P * (C + 1) * 4) + pad64(P * C * NBINS) +
+         pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4);
+}
+
+int orc_export(const orc_state *s, void *dst, size_t bytes) {
+  if (!s || !dst) return -1;
+  const orc_params *p = &s->p;
+  if (bytes < orc_canonical_bytes(p)) return -1;
+  const size_t P = (size_t)s->npix;
+  const size_t C = (size_t)p->channels, K = (size_t)p->K;
+  char *o = (char *)dst;
+  memset(o, 0, orc_canonical_bytes(p));
+  uint32_t hdr32[2] = {0x31474F43u, 1u};
+  int32_t hdri[6] = {p->width, p->height, p->channels, p->K, p->dtype, s->n_train};
+  int64_t fr = s->frame;
+  memcpy(o, hdr32, 8);
+  memcpy(o + 8, hdri, 24);
+  memcpy(o + 32, &fr, 8);
+  size_t off = 64;
+  memcpy(o + off, s->gmm, P * K * (C + 2) * 4);
+  off += pad64(P * K * (C + 2) * 4);
+  memcpy(o + off, s->rga, P * (C + 1) * 4);
+  off += pad64(P * (C + 1) * 4);
+  memcpy(o + off, s->table, P * C * NBINS);
+  off += pad64(P * C * NBINS);
+  memcpy(o + off, s->cnt, P * 3 * 2);
+  off += pad64(P * 3 * 2);
+  memcpy(o + off, s->label, P);
+  off += pad64(P);
+  memcpy(o + off, s->prev, P * C * 4);
+  return 0;
+}
