@@ -1,0 +1,259 @@
+"""ctypes binding of libcog.so (include/cog.h), argument marshalling only.
+
+Every step of the method runs in the HIP library; this module only turns
+Python objects into pointers and sizes.  Frames and masks may be numpy arrays
+(host memory) or torch tensors (host or HIP device memory); torch is used only
+for device memory and streams.  There is no fallback: if the library is not
+built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcog.so")
+
+COG_OK, COG_E_INVALID, COG_E_OOM, COG_E_STATE, COG_E_DEVICE, COG_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+COG_U8, COG_F32 = 0, 1
+COG_STAGE_FD, COG_STAGE_RGA, COG_STAGE_KDE, COG_STAGE_ALL = 1, 2, 4, 7
+COG_PATH_CASCADE, COG_PATH_GMM = 0, 1
+
+STATUS_NAMES = {0: "COG_OK", -1: "COG_E_INVALID", -2: "COG_E_OOM", -3: "COG_E_STATE",
+                -4: "COG_E_DEVICE", -5: "COG_E_UNSUPPORTED"}
+
+
+class cog_params(ct.Structure):
+    _fields_ = [
+        ("struct_size", ct.c_uint32),
+        ("width", ct.c_int32), ("height", ct.c_int32), ("channels", ct.c_int32),
+        ("dtype", ct.c_int32), ("in_lo", ct.c_float), ("in_hi", ct.c_float),
+        ("K", ct.c_int32),
+        ("alpha", ct.c_float), ("T", ct.c_float), ("lam", ct.c_float),
+        ("var_init", ct.c_float), ("var_min", ct.c_float),
+        ("stage_mask", ct.c_uint32),
+        ("tau_fd", ct.c_float), ("lambda_rga", ct.c_float), ("alpha_rga", ct.c_float),
+        ("kde_bins", ct.c_int32), ("kde_h", ct.c_float), ("res_e1", ct.c_float), ("res_e2", ct.c_float),
+        ("lambda_m", ct.c_float), ("conf_thr", ct.c_float), ("p_null", ct.c_float),
+        ("kappa_alpha", ct.c_float), ("illum_frac", ct.c_float),
+        ("path", ct.c_int32), ("tile_px", ct.c_int32),
+    ]
+
+
+class cog_step_info(ct.Structure):
+    _fields_ = [
+        ("frame", ct.c_int64), ("n_stage", ct.c_int64 * 4), ("n3_bg", ct.c_int64),
+        ("n_fg", ct.c_int64), ("illum_flag", ct.c_int32), ("reserved", ct.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return dict(frame=self.frame, n0=self.n_stage[0], n1=self.n_stage[1], n2=self.n_stage[2],
+                    n3=self.n_stage[3], n3_bg=self.n3_bg, n_fg=self.n_fg, illum_flag=self.illum_flag)
+
+
+class CogError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libcog.so is not built ({LIB_PATH}); run paper_1705_09339_amd/build.py")
+    L = ct.CDLL(LIB_PATH)
+    P, V = ct.POINTER, ct.c_void_p
+    sig = {
+        "cog_default_params": ([P(cog_params), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32], ct.c_int),
+        "cog_state_bytes": ([P(cog_params), P(ct.c_size_t)], ct.c_int),
+        "cog_canonical_bytes": ([P(cog_params), P(ct.c_size_t)], ct.c_int),
+        "cog_create": ([P(cog_params), V, V, ct.c_size_t, P(V)], ct.c_int),
+        "cog_train_prior": ([V, V, ct.c_int32, ct.c_int32], ct.c_int),
+        "cog_step": ([V, V, ct.c_int32, V, ct.c_int32, P(cog_step_info)], ct.c_int),
+        "cog_step_frames": ([V, V, ct.c_int32, ct.c_int32, V, ct.c_int32, P(cog_step_info)], ct.c_int),
+        "cog_reset": ([V], ct.c_int),
+        "cog_destroy": ([V], None),
+        "cog_export_state": ([V, V, ct.c_size_t], ct.c_int),
+        "cog_import_state": ([V, V, ct.c_size_t], ct.c_int),
+        "cog_kde_weights": ([ct.c_float, P(ct.c_uint16)], ct.c_int),
+        "cog_last_error": ([V], ct.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+EXPORTED = ("cog_default_params", "cog_state_bytes", "cog_canonical_bytes", "cog_create",
+            "cog_train_prior", "cog_step", "cog_step_frames", "cog_reset", "cog_destroy",
+            "cog_export_state", "cog_import_state", "cog_kde_weights", "cog_last_error")
+
+
+def _check(rc: int, h=None):
+    if rc != COG_OK:
+        msg = lib.cog_last_error(h)
+        raise CogError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a):
+    """(address, on_device, keepalive) of a numpy array or torch tensor."""
+    if a is None:
+        return None, 0, None
+    if isinstance(a, np.ndarray):
+        a = np.ascontiguousarray(a)
+        return a.ctypes.data, 0, a
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), 1 if a.is_cuda else 0, a
+    raise TypeError(f"unsupported buffer type {type(a)}")
+
+
+# ---- functions with the C names ------------------------------------------------
+
+def cog_default_params(width: int, height: int, channels: int = 3, dtype: int = COG_U8,
+                       K: int = 3, **overrides) -> cog_params:
+    p = cog_params()
+    _check(lib.cog_default_params(ct.byref(p), width, height, channels, dtype, K))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def cog_state_bytes(p: cog_params) -> int:
+    n = ct.c_size_t(0)
+    _check(lib.cog_state_bytes(ct.byref(p), ct.byref(n)))
+    return n.value
+
+
+def cog_canonical_bytes(p: cog_params) -> int:
+    n = ct.c_size_t(0)
+    _check(lib.cog_canonical_bytes(ct.byref(p), ct.byref(n)))
+    return n.value
+
+
+def cog_create(p: cog_params, stream=None, device_state=None) -> int:
+    """stream: a torch.cuda.Stream, a raw hipStream_t int, or None (default).
+    device_state: optional torch uint8 tensor on the device."""
+    h = ct.c_void_p(0)
+    sptr = None
+    if stream is not None:
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    dptr, nbytes = None, 0
+    if device_state is not None:
+        dptr, on_dev, _ = _ptr(device_state)
+        if not on_dev:
+            raise ValueError("device_state must be device memory")
+        nbytes = device_state.numel() * device_state.element_size()
+    _check(lib.cog_create(ct.byref(p), sptr, dptr, nbytes, ct.byref(h)))
+    return h.value
+
+
+def cog_train_prior(h: int, frames) -> None:
+    ptr, dev, keep = _ptr(frames)
+    _check(lib.cog_train_prior(h, ptr, len(frames), dev), h)
+    del keep
+
+
+def cog_step(h: int, frame, mask_out=None, want_info: bool = False) -> Optional[dict]:
+    fp, fdev, k1 = _ptr(frame)
+    mp, mdev, k2 = _ptr(mask_out)
+    info = cog_step_info() if want_info else None
+    _check(lib.cog_step(h, fp, fdev, mp, mdev, ct.byref(info) if info is not None else None), h)
+    del k1, k2
+    return info.as_dict() if info is not None else None
+
+
+def cog_step_frames(h: int, frames, masks_out=None, want_info: bool = False):
+    n = len(frames)
+    fp, fdev, k1 = _ptr(frames)
+    mp, mdev, k2 = _ptr(masks_out)
+    infos = (cog_step_info * n)() if want_info else None
+    _check(lib.cog_step_frames(h, fp, n, fdev, mp, mdev, infos), h)
+    del k1, k2
+    return [i.as_dict() for i in infos] if infos is not None else None
+
+
+def cog_reset(h: int) -> None:
+    _check(lib.cog_reset(h), h)
+
+
+def cog_destroy(h: int) -> None:
+    lib.cog_destroy(h)
+
+
+def cog_export_state(h: int, p: cog_params) -> bytes:
+    n = cog_canonical_bytes(p)
+    buf = np.zeros(n, dtype=np.uint8)
+    _check(lib.cog_export_state(h, buf.ctypes.data, n), h)
+    return buf.tobytes()
+
+
+def cog_import_state(h: int, blob: bytes) -> None:
+    a = np.frombuffer(blob, dtype=np.uint8)
+    _check(lib.cog_import_state(h, a.ctypes.data, a.size), h)
+
+
+def cog_kde_weights(hw: float = 8.0) -> np.ndarray:
+    out = np.zeros((16, 256), dtype=np.uint16)
+    _check(lib.cog_kde_weights(hw, out.ctypes.data_as(ct.POINTER(ct.c_uint16))))
+    return out
+
+
+def cog_last_error(h: Optional[int] = None) -> str:
+    m = lib.cog_last_error(h)
+    return m.decode() if m else ""
+
+
+class CogStream:
+    """One stream's context: owns the handle, forwards to the C calls."""
+
+    def __init__(self, params: cog_params, stream=None, device_state=None):
+        self.params = params
+        self.h = cog_create(params, stream, device_state)
+
+    def train_prior(self, frames):
+        cog_train_prior(self.h, frames)
+
+    def step(self, frame, mask_out=None, want_info=False):
+        return cog_step(self.h, frame, mask_out, want_info)
+
+    def step_frames(self, frames, masks_out=None, want_info=False):
+        return cog_step_frames(self.h, frames, masks_out, want_info)
+
+    def reset(self):
+        cog_reset(self.h)
+
+    def export_state(self) -> bytes:
+        return cog_export_state(self.h, self.params)
+
+    def import_state(self, blob: bytes):
+        cog_import_state(self.h, blob)
+
+    def close(self):
+        if self.h:
+            cog_destroy(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,63 @@
+// Library-private declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cog {
+
+constexpr int kNT = 256;        // threads per workgroup (4 wave64)
+constexpr int kNW = kNT / 64;   // waves per workgroup
+constexpr int kBins = 16;       // prior bins per channel
+constexpr int kStat = 8;        // counters per statistics slot
+
+// Floats per per-pixel mixture record: {w[K], var[K], mu[K][C]} padded to 16 B.
+__host__ __device__ constexpr int rec_floats(int C, int K) { return ((K * (C + 2)) + 3) & ~3; }
+// Floats per running-average record {mu_r[C], var_r}.
+__host__ __device__ constexpr int rga_floats(int C) { return C == 3 ? 4 : 2; }
+// Bytes per prior record {t[C][16] u8, cnt[3] u16} padded to 32/64 B.
+__host__ __device__ constexpr int prior_bytes(int C) { return C == 3 ? 64 : 32; }
+
+// Scalar parameters as the kernels use them (squares and complements
+// rounded once to binary32 on the host).
+struct KParams {
+  float alpha, T, lam2, var_init, var_min;
+  float tau_fd, lam_r2, alpha_rga, one_m_alpha_rga;
+  float res_e1, res_e2, lam_m2, conf_thr, p_null, kappa;
+  float nm1;            // n_train - 1
+  float in_lo, q_scale; // f32 input quantisation: floor((v - in_lo) * q_scale)
+  uint32_t stage_mask;
+};
+
+// Device state of one stream (see the host planner for sizes).
+struct Buffers {
+  float *gmm;                  // cascade: AoS records; baseline: 64-pixel AoSoA groups
+  float *rga;                  // rga_floats(C) per pixel
+  uint8_t *prior;              // prior_bytes(C) per pixel
+  void *prev;                  // C values per pixel (u8 or f32, as the input)
+  unsigned long long *labels;  // 1 bit per pixel, bit p&63 of word p>>6
+  const uint16_t *kdew;        // prior kernel weights, level-major [256][16]
+  int64_t P;
+};
+
+// A run of consecutive frames handed to one launch.
+struct Frames {
+  const void *x;       // frame 0 (HWC)
+  int64_t stride;      // elements between frames
+  uint8_t *mask;       // mask of frame 0 or nullptr
+  int64_t mstride;     // bytes between masks
+  uint32_t *partials;  // [nframes][nslots][kStat] or nullptr
+  int nslots;
+  int nframes;
+};
+
+// Launchers (cog_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_train(int C, int K, bool f32in, bool prior, bool aos, const Buffers &b,
+                        const void *frames, int64_t stride, int n, const KParams &kp,
+                        hipStream_t s);
+hipError_t launch_cascade(int C, int K, bool f32in, int ppt, const Buffers &b, const Frames &fr,
+                          const KParams &kp, hipStream_t s);
+hipError_t launch_gmm(int C, int K, bool f32in, const Buffers &b, const Frames &fr,
+                      const KParams &kp, hipStream_t s);
+
+}  // namespace cog
