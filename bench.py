@@ -1,0 +1,310 @@
+"""Throughput of the CoG cascade vs the plain mixture on one MI355X.
+
+One step = the whole hot path over one synthetic stream already resident in
+HBM: the prior-training launch over the first N frames, then the cascade
+over the remaining frames.  The plain Stauffer-Grimson baseline processes the
+same stream (warm-up over N frames, then a mixture step per frame) in its own
+timed region.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel-frames/s CoG vs full-GMM on 1 GPU (% HBM roofline); p99 frame latency"
+HBM_PEAK_GBS = 8000.0
+# vector ALU issue rate without packed or fused ops: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="surveil-640x480-k5")
+    ap.add_argument("--chunk", type=int, default=0, help="frames per cascade launch (0 = all)")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def alg_bytes_cascade(occ, P, F, K, C=3):
+    """Algorithmic HBM bytes of one multi-frame cascade launch over F frames.
+
+    Per pixel-frame: the input value (C B) and the mask byte; the mixture
+    record read and written (K(C+2) floats each way) for every pixel that
+    reaches S3.  Per pixel per launch: the 64-byte prior record (staged in
+    LDS once), the previous value (C B) and running average (16 B) read and
+    written, label bits read and written.
+    """
+    per_frame = P * (C + 1) * F
+    mix = 2 * K * (C + 2) * 4 * occ["n3"]
+    per_launch = P * (64 + 2 * C + 2 * 16 + 2 / 8)
+    return per_frame + mix + per_launch
+
+
+def alg_bytes_gmm(P, F, K, C=3):
+    """Plain mixture, F frames in one launch: input + mask per pixel-frame,
+    the mixture record read and written once per launch, label bits."""
+    return P * (C + 1) * F + P * (2 * K * (C + 2) * 4 + C + 2 / 8)
+
+
+def alg_bytes_train(P, N, K, C=3):
+    """Training launch: N frames of input; writes the mixture, the running
+    average, the 64-byte prior record, the previous value and label bits."""
+    return P * (C * N + K * (C + 2) * 4 + 16 + 64 + C + 1 / 8)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("cog_kernels.hip", "cog_device.h"):
+        with open(os.path.join(ROOT, "paper_1705_09339_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        b = int(float(kv["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+    return {"bytes_per_launch": b, "note": kv.get("note", "")}
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the method has no cross-GPU exchange and this "
+              "build measures the single-GPU kernel (see the sharding notes in DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_1705_09339_amd import cog as C
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    spec = synth.preset(args.workload)
+    P, T, N, K = spec.pixels, spec.frames, spec.n_train, spec.K
+    F = T - N
+    log(f"workload {spec.name}: {spec.width}x{spec.height} x {T} frames, N={N}, K={K}")
+    t0 = time.time()
+    frames = synth.make_stream(spec)
+    log(f"generated in {time.time() - t0:.1f} s")
+    dev = torch.from_numpy(frames).cuda()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    masks = torch.empty((F, P), dtype=torch.uint8, device="cuda")
+
+    def make(path):
+        p = C.cog_default_params(spec.width, spec.height, 3, C.COG_U8, K, path=path,
+                                 tile_px=args.tile)
+        return C.CogStream(p, stream=stream)
+
+    chunk = args.chunk or F
+
+    def job(ctx, ev=None):
+        ctx.reset()
+        if ev:
+            ev[0].record(stream)
+        ctx.train_prior(dev[:N])
+        if ev:
+            ev[1].record(stream)
+        for t0_ in range(0, F, chunk):
+            t1_ = min(F, t0_ + chunk)
+            ctx.step_frames(dev[N + t0_:N + t1_], masks[t0_:t1_])
+        if ev:
+            ev[2].record(stream)
+
+    def timed(ctx, name):
+        for _ in range(args.warmup):
+            job(ctx)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            job(ctx, evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        tr = [e[0].elapsed_time(e[1]) for e in evs]
+        ca = [e[1].elapsed_time(e[2]) for e in evs]
+        log(f"{name}: {wall / args.steps * 1e3:.3f} ms/step, train {np.mean(tr):.3f} ms, "
+            f"frames {np.mean(ca):.3f} ms")
+        return wall, float(np.mean(tr)), float(np.mean(ca))
+
+    # a plain copy of known size: the reference that scales the HBM byte
+    # counters of the profiled runs
+    calib = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    calib.copy_(dev.view(-1)[:64 << 20])
+    torch.cuda.synchronize()
+    del calib
+
+    cog_ctx = make(C.COG_PATH_CASCADE)
+    wall, tr_ms, ca_ms = timed(cog_ctx, "cog")
+    # level occupancy of the same stream, taken through the 128-pixel tile
+    # kernel (identical results for every tile size) so that the timed
+    # kernel's launches all cover the same frame count
+    p_occ = C.cog_default_params(spec.width, spec.height, 3, C.COG_U8, K, tile_px=128)
+    occ_ctx = C.CogStream(p_occ, stream=stream)
+    occ_ctx.train_prior(dev[:N])
+    infos = occ_ctx.step_frames(dev[N:], masks, want_info=True)
+    occ_ctx.close()
+    occ = {k: int(sum(i[k] for i in infos)) for k in ("n0", "n1", "n2", "n3", "n3_bg", "n_fg")}
+
+    gmm_ctx = make(C.COG_PATH_GMM)
+    g_wall, g_tr_ms, g_ca_ms = timed(gmm_ctx, "gmm")
+
+    # per-frame streaming: one cog_step per frame, latency submit -> mask ready
+    lat = {}
+    if not args.no_latency:
+        cog_ctx.reset()
+        cog_ctx.train_prior(dev[:N])
+        torch.cuda.synchronize()
+        wall_ms, gpu_ms = [], []
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for t in range(F):
+            ts = time.perf_counter()
+            e0.record(stream)
+            cog_ctx.step(dev[N + t], masks[t])
+            e1.record(stream)
+            e1.synchronize()
+            wall_ms.append((time.perf_counter() - ts) * 1e3)
+            gpu_ms.append(e0.elapsed_time(e1))
+        cog_ctx.reset()
+        cog_ctx.train_prior(dev[:N])
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for t in range(F):
+            cog_ctx.step(dev[N + t], masks[t])
+        torch.cuda.synchronize()
+        stream_s = time.perf_counter() - ts
+        lat = {"p50_ms": round(pct(wall_ms, 50), 4), "p99_ms": round(pct(wall_ms, 99), 4),
+               "kernel_p50_ms": round(pct(gpu_ms, 50), 4), "kernel_p99_ms": round(pct(gpu_ms, 99), 4),
+               "per_frame_mpx_s": round(P * F / stream_s / 1e6, 1),
+               "note": "one cog_step per frame on device-resident frames, wall time from "
+                       "submission to mask ready"}
+        log(f"latency p50 {lat['p50_ms']} ms p99 {lat['p99_ms']} ms; per-frame stream "
+            f"{lat['per_frame_mpx_s']} Mpx/s")
+
+    cog_ctx.close()
+    gmm_ctx.close()
+
+    value = P * T * args.steps / wall / 1e6
+    g_value = P * T * args.steps / g_wall / 1e6
+    # dominant kernel of the step and its roofline
+    b_casc = alg_bytes_cascade(occ, P, F, K)
+    b_train = alg_bytes_train(P, N, K)
+    tile = args.tile or 64
+    casc_name = "k_cascade_d" if tile == 64 else ("k_cascade_w" if tile == 128 else "k_cascade")
+    dominant = casc_name if ca_ms >= tr_ms else "k_train"
+    dom_ms = ca_ms if dominant == casc_name else tr_ms
+    dom_bytes = b_casc if dominant == casc_name else b_train
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, spec.name)
+    roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "alg_bytes_per_launch": int(dom_bytes), "launch_ms": round(dom_ms, 4)}
+    if traffic:
+        roof["traffic_note"] = traffic["note"]
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mpixel-frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "width": spec.width, "height": spec.height,
+                   "frames": T, "n_train": N, "K": K, "input": "u8 RGB",
+                   "launches_per_step": 1 + math.ceil(F / chunk), "tile_px": tile},
+        "gmm": {"value": round(g_value, 1), "ms_per_step": round(g_wall / args.steps * 1e3, 4),
+                "train_ms": round(g_tr_ms, 4), "frames_ms": round(g_ca_ms, 4)},
+        "speedup_vs_gmm": round(value / g_value, 3),
+        "online": {"cog_mpx_s": round(P * F / (ca_ms * 1e-3) / 1e6, 1),
+                   "gmm_mpx_s": round(P * F / (g_ca_ms * 1e-3) / 1e6, 1),
+                   "train_ms": round(tr_ms, 4), "frames_ms": round(ca_ms, 4)},
+        "occupancy": {k: round(v / (P * F), 5) for k, v in occ.items()},
+        "latency": lat,
+        "roofline": roof,
+    }
+
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(frames, spec, args.cpu_seconds)
+
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(frames, spec, budget_s):
+    """The oracle (single thread) on a pixel sample of the same stream."""
+    from oracle import oracle as O
+
+    P, T, N, K = spec.pixels, spec.frames, spec.n_train, spec.K
+    flat = frames.reshape(T, P, 3)
+
+    def run(stride):
+        idx = np.arange(0, P, stride)
+        sub = np.ascontiguousarray(flat[:, idx][:, None])
+        orc = O.Oracle(O.make_params(len(idx), 1, 3, K))
+        ts = time.perf_counter()
+        orc.train(sub[:N])
+        for t in range(N, T):
+            orc.step(sub[t])
+        el = time.perf_counter() - ts
+        orc.close()
+        return len(idx), el
+
+    n0, e0 = run(256)
+    stride = max(1, int(math.ceil(256 * e0 / budget_s)))
+    n, el = run(stride)
+    log(f"cpu oracle: {n} px x {T} frames in {el:.1f} s")
+    return {"value": round(n * T / el / 1e6, 3), "unit": "Mpixel-frames/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"every {stride}th pixel ({n} px) of all {T} frames: training over {N}, "
+                      f"cascade over {T - N}",
+            "host": platform.processor() or platform.machine(), "seconds": round(el, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -92,7 +92,7 @@ typedef struct {
   float kappa_alpha;       /* mixture rate alpha*(1 - kappa_alpha*C) [0.5] */
   float illum_frac;        /* illumination flag when n3 > illum_frac*pixels [0.7] */
   int32_t path;            /* cog_path [COG_PATH_CASCADE] */
-  int32_t tile_px;         /* pixels per workgroup tile: 0 (auto), 256, 512 or 1024 */
+  int32_t tile_px;         /* cascade pixels per tile: 0 (auto = 64), 64, 128, 256, 512, 1024 */
 } cog_params;
 
 /* Per-frame statistics (the occupancy of the cascade levels, §2 "Cascade of

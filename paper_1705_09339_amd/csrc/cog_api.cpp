@@ -28,8 +28,8 @@ struct Plan {
   int64_t P = 0, Ppad = 0;
   int C = 0, K = 0, R = 0, RG = 0, PB = 0, sin = 1;
   int tile = 0, ppt = 1, ntiles = 0, nslots = 0;
-  size_t off_gmm = 0, off_rga = 0, off_prior = 0, off_prev = 0, off_labels = 0, off_kdew = 0,
-         off_partials = 0, total = 0;
+  size_t off_gmm = 0, off_rga = 0, off_prior = 0, off_cnt = 0, off_prev = 0, off_labels = 0,
+         off_kdew = 0, off_partials = 0, total = 0;
 };
 
 }  // namespace
@@ -90,8 +90,9 @@ std::string check_params(const cog_params *p) {
   if (!(p->kappa_alpha >= 0.0f && p->kappa_alpha <= 1.0f)) return "kappa_alpha must be in [0, 1]";
   if (!(p->illum_frac >= 0.0f)) return "illum_frac must be >= 0";
   if (p->path != COG_PATH_CASCADE && p->path != COG_PATH_GMM) return "unknown path";
-  if (p->tile_px != 0 && p->tile_px != 256 && p->tile_px != 512 && p->tile_px != 1024)
-    return "tile_px must be 0, 256, 512 or 1024";
+  if (p->tile_px != 0 && p->tile_px != 64 && p->tile_px != 128 && p->tile_px != 256 &&
+      p->tile_px != 512 && p->tile_px != 1024)
+    return "tile_px must be 0, 64, 128, 256, 512 or 1024";
   return std::string();
 }
 
@@ -108,9 +109,9 @@ Plan make_plan(const cog_params *p) {
   const bool cascade = p->path == COG_PATH_CASCADE;
   if (cascade) {
     int tile = p->tile_px;
-    if (tile == 0) tile = 256;
+    if (tile == 0) tile = 64;
     pl.tile = tile;
-    pl.ppt = tile / cog::kNT;
+    pl.ppt = tile >= cog::kNT ? tile / cog::kNT : tile / 64;
     pl.ntiles = (int)((pl.P + tile - 1) / tile);
     pl.nslots = pl.ntiles;
   } else {
@@ -126,6 +127,8 @@ Plan make_plan(const cog_params *p) {
   if (cascade) off += align256((size_t)pl.Ppad * pl.RG * 4);
   pl.off_prior = off;
   if (cascade) off += align256((size_t)pl.Ppad * pl.PB);
+  pl.off_cnt = off;
+  if (cascade) off += align256((size_t)pl.Ppad * 8);
   pl.off_prev = off;
   off += align256((size_t)pl.Ppad * pl.C * pl.sin);
   pl.off_labels = off;
@@ -178,15 +181,6 @@ cog::KParams make_kparams(const cog_params *p, int32_t n_train) {
   k.q_scale = 256.0f / (p->in_hi - p->in_lo);
   k.stage_mask = p->stage_mask;
   return k;
-}
-
-bool is_device_ptr(const void *ptr) {
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
 cog_status ensure_stage(cog_ctx *h, size_t in_bytes, size_t mask_bytes) {
@@ -245,7 +239,7 @@ cog_status run_frames(cog_ctx *h, const void *dframes, int n, uint8_t *dmasks, b
     fr.nframes = cnt;
     hipError_t e;
     if (h->p.path == COG_PATH_CASCADE)
-      e = cog::launch_cascade(pl.C, pl.K, h->p.dtype == COG_F32, pl.ppt, h->buf, fr, h->kp,
+      e = cog::launch_cascade(pl.C, pl.K, h->p.dtype == COG_F32, pl.tile, h->buf, fr, h->kp,
                               h->stream);
     else
       e = cog::launch_gmm(pl.C, pl.K, h->p.dtype == COG_F32, h->buf, fr, h->kp, h->stream);
@@ -365,6 +359,7 @@ cog_status cog_create(const cog_params *p, void *hip_stream, void *device_state,
   h->buf.gmm = reinterpret_cast<float *>(h->dstate + pl.off_gmm);
   h->buf.rga = reinterpret_cast<float *>(h->dstate + pl.off_rga);
   h->buf.prior = reinterpret_cast<uint8_t *>(h->dstate + pl.off_prior);
+  h->buf.cnt = reinterpret_cast<uint16_t *>(h->dstate + pl.off_cnt);
   h->buf.prev = h->dstate + pl.off_prev;
   h->buf.labels = reinterpret_cast<unsigned long long *>(h->dstate + pl.off_labels);
   h->buf.kdew = reinterpret_cast<const uint16_t *>(h->dstate + pl.off_kdew);
@@ -523,8 +518,9 @@ cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes) {
     uint8_t *t = reinterpret_cast<uint8_t *>(o + off);
     for (size_t p = 0; p < P; ++p) std::memcpy(t + p * C * 16, pr + p * pl.PB, C * 16);
     off += pad64(P * C * 16);
+    const uint16_t *cs = reinterpret_cast<const uint16_t *>(raw.data() + pl.off_cnt);
     uint16_t *cn = reinterpret_cast<uint16_t *>(o + off);
-    for (size_t p = 0; p < P; ++p) std::memcpy(cn + p * 3, pr + p * pl.PB + C * 16, 6);
+    for (size_t p = 0; p < P; ++p) std::memcpy(cn + p * 3, cs + p * 4, 6);
     off += pad64(P * 3 * 2);
   } else {
     off += pad64(P * C * 16) + pad64(P * 3 * 2);
@@ -587,7 +583,15 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
     for (size_t p = 0; p < P; ++p) std::memcpy(pr + p * pl.PB, t + p * C * 16, C * 16);
     off += pad64(P * C * 16);
     const uint16_t *cn = reinterpret_cast<const uint16_t *>(in + off);
-    for (size_t p = 0; p < P; ++p) std::memcpy(pr + p * pl.PB + C * 16, cn + p * 3, 6);
+    uint16_t *cs = reinterpret_cast<uint16_t *>(raw.data() + pl.off_cnt);
+    const float nm1 = (float)(hi[5] - 1);
+    for (size_t p = 0; p < P; ++p) {
+      std::memcpy(cs + p * 4, cn + p * 3, 6);
+      // confidence weights as the training kernel stores them
+      float abg[3];
+      for (int i = 0; i < 3; ++i) abg[i] = (float)cn[p * 3 + i] / nm1;
+      std::memcpy(pr + p * pl.PB + C * 16, abg, 12);
+    }
     off += pad64(P * 3 * 2);
   } else {
     off += pad64(P * C * 16) + pad64(P * 3 * 2);

@@ -15,7 +15,7 @@ constexpr int kStat = 8;        // counters per statistics slot
 __host__ __device__ constexpr int rec_floats(int C, int K) { return ((K * (C + 2)) + 3) & ~3; }
 // Floats per running-average record {mu_r[C], var_r}.
 __host__ __device__ constexpr int rga_floats(int C) { return C == 3 ? 4 : 2; }
-// Bytes per prior record {t[C][16] u8, cnt[3] u16} padded to 32/64 B.
+// Bytes per prior record {t[C][16] u8, a, b, g f32} padded to 32/64 B.
 __host__ __device__ constexpr int prior_bytes(int C) { return C == 3 ? 64 : 32; }
 
 // Scalar parameters as the kernels use them (squares and complements
@@ -34,6 +34,7 @@ struct Buffers {
   float *gmm;                  // cascade: AoS records; baseline: 64-pixel AoSoA groups
   float *rga;                  // rga_floats(C) per pixel
   uint8_t *prior;              // prior_bytes(C) per pixel
+  uint16_t *cnt;               // residue counts, 4 u16 per pixel (export only)
   void *prev;                  // C values per pixel (u8 or f32, as the input)
   unsigned long long *labels;  // 1 bit per pixel, bit p&63 of word p>>6
   const uint16_t *kdew;        // prior kernel weights, level-major [256][16]
@@ -55,7 +56,7 @@ struct Frames {
 hipError_t launch_train(int C, int K, bool f32in, bool prior, bool aos, const Buffers &b,
                         const void *frames, int64_t stride, int n, const KParams &kp,
                         hipStream_t s);
-hipError_t launch_cascade(int C, int K, bool f32in, int ppt, const Buffers &b, const Frames &fr,
+hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, const Frames &fr,
                           const KParams &kp, hipStream_t s);
 hipError_t launch_gmm(int C, int K, bool f32in, const Buffers &b, const Frames &fr,
                       const KParams &kp, hipStream_t s);

@@ -263,6 +263,77 @@ __device__ __forceinline__ const void *frame_ptr(const void *x, int64_t stride, 
   return static_cast<const uint8_t *>(x) + (int64_t)f * stride;
 }
 
+
+// Raw input registers: the load result is kept untouched until the frame it
+// belongs to is processed, so a prefetch issued one frame early is not waited
+// for before its first real use.
+template <bool F32>
+struct RawT { using type = uint32_t; };
+template <>
+struct RawT<true> { using type = float; };
+
+template <int C, bool F32>
+__device__ __forceinline__ void raw_load(const void *base, int64_t p,
+                                         typename RawT<F32>::type (&r)[C]) {
+  if constexpr (F32) {
+    const float *q = static_cast<const float *>(base) + p * C;
+#pragma unroll
+    for (int c = 0; c < C; ++c) r[c] = __builtin_nontemporal_load(q + c);
+  } else {
+    const uint8_t *q = static_cast<const uint8_t *>(base) + p * C;
+#pragma unroll
+    for (int c = 0; c < C; ++c) r[c] = (uint32_t)__builtin_nontemporal_load(q + c);
+  }
+}
+
+template <int C, bool F32>
+__device__ __forceinline__ void raw_to_float(const typename RawT<F32>::type (&r)[C], float (&x)[C]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) x[c] = (float)r[c];
+}
+
+
+// u8 input, one wave per 64 consecutive pixels: the wave's 64*C bytes are
+// read as the dwords of the 4-byte-aligned window that covers them (lane i
+// loads dword i), and each lane later picks its C bytes out with a lane
+// permute.  Aligned dwords never straddle a page, so the at most 3 bytes read
+// beyond either end of the run cannot fault.  npx >= 1 valid pixels.
+template <int C>
+__device__ __forceinline__ uint32_t u8win_load(const uint8_t *frame, int64_t first_px, int npx,
+                                               int lane) {
+  const uint8_t *start = frame + first_px * C;
+  const int mis = (int)(reinterpret_cast<uintptr_t>(start) & 3);
+  // derived by pointer arithmetic so that the load stays a global (not flat) load
+  const uint32_t *al = reinterpret_cast<const uint32_t *>(start - mis);
+  const int nd = (mis + npx * C + 3) >> 2;
+  return __builtin_nontemporal_load(al + (lane < nd ? lane : nd - 1));
+}
+
+template <int C>
+__device__ __forceinline__ void u8win_extract(uint32_t raw, const uint8_t *frame, int64_t first_px,
+                                              int lane, float (&x)[C]) {
+  const int mis = (int)(reinterpret_cast<uintptr_t>(frame + first_px * C) & 3);
+  const int o = mis + C * lane;
+  const int w0 = o >> 2;
+  const uint32_t d0 = (uint32_t)__builtin_amdgcn_ds_bpermute(w0 << 2, (int)raw);
+  if constexpr (C == 1) {
+    x[0] = (float)((d0 >> (8 * (o & 3))) & 0xffu);
+  } else {
+    const uint32_t d1 = (uint32_t)__builtin_amdgcn_ds_bpermute((w0 + 1) << 2, (int)raw);
+    const uint32_t win = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)(o & 3));
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = (float)((win >> (8 * c)) & 0xffu);
+  }
+}
+
+// Compiler-level ordering of LDS accesses between the lanes of one wave (the
+// hardware executes a wave's LDS instructions in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Prior quantisation: u8 levels directly; f32 values onto 256 levels.
 template <bool F32>
 __device__ __forceinline__ int quant(float v, const KParams &kp) {
@@ -293,6 +364,33 @@ __device__ __forceinline__ int lane_prefix(unsigned long long bal) {
                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
 }
 
+
+// S2 (§2 "Confidence Measure", "Cascade of Gaussians CoG"): the scene-prior
+// probability of x from the pixel's u8 KDE table (channels independent, so
+// the product of the per-channel entries), then C = a P + b D + g M with the
+// weights a, b, g from the training residue histogram, D the frame-difference
+// similarity and M the distance to the running average; a is dropped when P
+// is below p_null (prior nullified).  rec is the pixel's prior record:
+// t[C][16] u8, then a, b, g as f32.
+template <int C, bool F32>
+__device__ __forceinline__ float confidence(const uint8_t *rec, const float (&x)[C], float dl,
+                                            float dr2, float var_r, const KParams &kp) {
+  uint32_t prod = 1u;
+#pragma unroll
+  for (int c = 0; c < C; ++c) prod = prod * (uint32_t)rec[c * kBins + (quant<F32>(x[c], kp) >> 4)];
+  const float ph = (float)prod / (C == 3 ? 16581375.0f : 255.0f);
+  const float *abg = reinterpret_cast<const float *>(rec + C * kBins);
+  float a = abg[0];
+  const float bw = abg[1];
+  const float g = abg[2];
+  if (ph < kp.p_null) a = 0.0f;
+  float dh = 1.0f - dl / kp.res_e2;
+  dh = dh < 0.0f ? 0.0f : dh;
+  float mh = 1.0f - dr2 / (kp.lam_m2 * var_r);
+  mh = mh < 0.0f ? 0.0f : mh;
+  return (a * ph + bw * dh) + g * mh;
+}
+
 // ============================================================================
 // Training phase: one thread per pixel walks the N training frames.
 //  - integer KDE bin masses acc[c][b] += W[b][q(x)] (weights staged in LDS,
@@ -301,9 +399,11 @@ __device__ __forceinline__ int lane_prefix(unsigned long long bal) {
 //  - the mixture warm-up (initialised from frame 0, stepped on 1..N-1).
 // Then the max-normalised u8 table, counts, mixture, running average (from
 // the dominant mode), previous frame and label are written once.
-template <int C, int K, bool F32>
+template <int C, int K, bool F32, bool PRIOR>
 __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, int64_t stride,
-                                               int n, KParams kp, int with_prior, int aos) {
+                                               int n, KParams kp) {
+  // the cascade keeps per-pixel mixture records; the baseline 64-pixel groups
+  constexpr bool with_prior = PRIOR, aos = PRIOR;
   __shared__ uint4 s_w[256 * kBins * 2 / 16];
   for (int i = threadIdx.x; i < 256 * kBins * 2 / 16; i += kNT)
     s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
@@ -326,7 +426,7 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
     mix_init<C, K>(m, x, kp.var_init);
     for (int j = 0; j < n; ++j) {
       load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j), p, x);
-      if (with_prior) {
+      if constexpr (with_prior) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const int v = quant<F32>(x[c], kp);
@@ -340,7 +440,7 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
         }
       }
       if (j >= 1) {
-        if (with_prior) {
+        if constexpr (with_prior) {
           const float dl = frame_delta<C>(x, xp);
           if (dl < kp.res_e1) cnt0++;
           else if (dl < kp.res_e2) cnt1++;
@@ -354,7 +454,7 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
       for (int c = 0; c < C; ++c) xp[c] = x[c];
     }
 
-    if (with_prior) {
+    if constexpr (with_prior) {
       constexpr int PB = prior_bytes(C);
       uint32_t words[PB / 4];
 #pragma unroll
@@ -372,8 +472,12 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
           words[byte >> 2] |= (t & 0xffu) << (8 * (byte & 3));
         }
       }
-      words[(C * kBins) / 4] = (cnt0 & 0xffffu) | (cnt1 << 16);
-      words[(C * kBins) / 4 + 1] = cnt2 & 0xffffu;
+      // confidence weights a, b, g = counts / (N - 1), divided once here
+      words[(C * kBins) / 4] = __float_as_uint((float)cnt0 / kp.nm1);
+      words[(C * kBins) / 4 + 1] = __float_as_uint((float)cnt1 / kp.nm1);
+      words[(C * kBins) / 4 + 2] = __float_as_uint((float)cnt2 / kp.nm1);
+      *reinterpret_cast<uint2 *>(b.cnt + p * 4) =
+          make_uint2((cnt0 & 0xffffu) | (cnt1 << 16), cnt2 & 0xffffu);
       uint4 *dst = reinterpret_cast<uint4 *>(b.prior + p * PB);
 #pragma unroll
       for (int i = 0; i < PB / 16; ++i)
@@ -385,7 +489,7 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
       for (int c = 0; c < C; ++c) rg[c] = m.mu[0][c];
       rg[C] = m.var[0];
     }
-    if (aos) rec_store<C, K>(b.gmm + p * rec_floats(C, K), m);
+    if constexpr (aos) rec_store<C, K>(b.gmm + p * rec_floats(C, K), m);
     else grp_store<C, K>(b.gmm, p, m);
     store_px<C, F32>(b.prev, p, xp);
   }
@@ -409,12 +513,16 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
 //            write the mask and count the level occupancy.
 // The dense state (previous value, label, running average) stays in
 // registers across the frames of one launch; only the deciding level adapts.
-template <int C, int K, bool F32, int PPT>
+// The next frame's input is prefetched into registers while the current one
+// is processed.  With LP (launches over many frames) the tile's prior records
+// are staged into LDS once, so S2 reads no HBM.
+template <int C, int K, bool F32, int PPT, bool LP>
 __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams kp) {
   constexpr int TILE = kNT * PPT;
   constexpr int R = rec_floats(C, K);
   constexpr int RG = rga_floats(C);
   constexpr int PB = prior_bytes(C);
+  __shared__ uint4 s_prior[LP ? TILE * PB / 16 : 1];
   __shared__ float s_x[TILE * C];
   __shared__ float s_dl[TILE];
   __shared__ float s_dr2[TILE];
@@ -456,22 +564,49 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
     }
   }
   if (tid < 2 * kStat) (&s_stat[0][0])[tid] = 0u;
-
-  for (int f = 0; f < fr.nframes; ++f) {
-    const void *xf = frame_ptr<C, F32>(fr.x, fr.stride, f);
-    float x[PPT][C];
-    int st[PPT], pre[PPT];
-    bool surv[PPT];
+  if constexpr (LP) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int64_t p = tile0 + j * kNT + tid;
       const int li = j * kNT + tid;
+      if (valid[j]) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(b.prior + p * PB);
+#pragma unroll
+        for (int q = 0; q < PB / 16; ++q) s_prior[li * (PB / 16) + q] = src[q];
+      }
+    }
+  }
+
+  // input of the next frame, in flight while the current frame is processed
+  float xn[PPT][C];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) xn[j][c] = 0.0f;
+    if (valid[j] && fr.nframes > 0)
+      load_px<C, F32>(fr.x, tile0 + j * kNT + tid, xn[j]);
+  }
+
+  for (int f = 0; f < fr.nframes; ++f) {
+    float x[PPT][C];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[j][c] = xn[j][c];
+    if (f + 1 < fr.nframes) {
+      const void *xf1 = frame_ptr<C, F32>(fr.x, fr.stride, f + 1);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j)
+        if (valid[j]) load_px<C, F32>(xf1, tile0 + j * kNT + tid, xn[j]);
+    }
+    int st[PPT], pre[PPT];
+    bool surv[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int li = j * kNT + tid;
       st[j] = -1;
       surv[j] = false;
-#pragma unroll
-      for (int c = 0; c < C; ++c) x[j][c] = 0.0f;
       if (valid[j]) {
-        load_px<C, F32>(xf, p, x[j]);
         const float dl = frame_delta<C>(x[j], xp[j]);
         if (fd_on && dl <= kp.tau_fd) {
           st[j] = 0;  // S0: repeat the previous label
@@ -549,22 +684,12 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
         float conf = 0.0f;
         bool accept = false;
         if (kde_on) {
-          const uint8_t *rec = b.prior + (tile0 + li) * PB;
-          uint32_t prod = 1u;
+          const uint8_t *rec = LP ? reinterpret_cast<const uint8_t *>(&s_prior[li * (PB / 16)])
+                                  : b.prior + (tile0 + li) * PB;
+          float xl[C];
 #pragma unroll
-          for (int c = 0; c < C; ++c)
-            prod = prod * (uint32_t)rec[c * kBins + (quant<F32>(s_x[li * C + c], kp) >> 4)];
-          const float ph = (float)prod / (C == 3 ? 16581375.0f : 255.0f);
-          const uint16_t *cn = reinterpret_cast<const uint16_t *>(rec + C * kBins);
-          float a = (float)cn[0] / kp.nm1;
-          const float bw = (float)cn[1] / kp.nm1;
-          const float g = (float)cn[2] / kp.nm1;
-          if (ph < kp.p_null) a = 0.0f;  // prior nullified
-          float dh = 1.0f - s_dl[li] / kp.res_e2;
-          dh = dh < 0.0f ? 0.0f : dh;
-          float mh = 1.0f - s_dr2[li] / (kp.lam_m2 * s_var[li]);
-          mh = mh < 0.0f ? 0.0f : mh;
-          conf = (a * ph + bw * dh) + g * mh;
+          for (int c = 0; c < C; ++c) xl[c] = s_x[li * C + c];
+          conf = confidence<C, F32>(rec, xl, s_dl[li], s_dr2[li], s_var[li], kp);
           accept = conf >= kp.conf_thr;
         }
         if (accept) {
@@ -690,6 +815,453 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
   }
 }
 
+
+// ============================================================================
+// The fused cascade with one wave per tile of 64*PPT consecutive pixels.
+// Same stages as k_cascade, but compaction, the S2/S3 work lists and the
+// hand-back of results stay inside one wave: no workgroup barrier, so every
+// wave walks its frames independently and the waves of a SIMD overlap each
+// other's memory and mixture latencies.
+template <int C, int K, bool F32, int PPT, bool LP>
+__global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams kp) {
+  constexpr int TILE = 64 * PPT;
+  constexpr int R = rec_floats(C, K);
+  constexpr int RG = rga_floats(C);
+  constexpr int PB = prior_bytes(C);
+  using raw_t = typename RawT<F32>::type;
+  __shared__ uint4 s_prior[LP ? TILE * PB / 16 : 1];
+  __shared__ float s_x[TILE * C];
+  __shared__ float s_dl[TILE];
+  __shared__ float s_dr2[TILE];
+  __shared__ float s_var[TILE];
+  __shared__ float s_conf[TILE];
+  __shared__ float s_rg[TILE * (C + 1)];
+  __shared__ uint16_t s_la[TILE];
+  __shared__ uint16_t s_lb[TILE];
+  __shared__ uint8_t s_res[TILE];  // bit0 foreground, bit1 re-seed, bits 2-3 stage
+
+  const int lane = threadIdx.x;
+  const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+  const bool fd_on = (kp.stage_mask & 1u) != 0;
+  const bool rga_on = (kp.stage_mask & 2u) != 0;
+  const bool kde_on = (kp.stage_mask & 4u) != 0;
+
+  float xp[PPT][C], rmu[PPT][C], rvar[PPT];
+  bool lab[PPT], dirty[PPT], valid[PPT];
+  int64_t pc[PPT];  // pixel index clamped into the frame (for the prefetch)
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int64_t p = tile0 + j * 64 + lane;
+    valid[j] = p < b.P;
+    pc[j] = valid[j] ? p : b.P - 1;
+    dirty[j] = false;
+    lab[j] = false;
+    rvar[j] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) xp[j][c] = rmu[j][c] = 0.0f;
+    if (valid[j]) {
+      const unsigned long long word = b.labels[p >> 6];
+      lab[j] = ((word >> lane) & 1ull) != 0;
+      load_px<C, F32>(b.prev, p, xp[j]);
+      const float *rg = b.rga + p * RG;
+#pragma unroll
+      for (int c = 0; c < C; ++c) rmu[j][c] = rg[c];
+      rvar[j] = rg[C];
+      if constexpr (LP) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(b.prior + p * PB);
+#pragma unroll
+        for (int q = 0; q < PB / 16; ++q) s_prior[(j * 64 + lane) * (PB / 16) + q] = src[q];
+      }
+    }
+  }
+
+  // input of the next frame, in flight while the current frame is processed
+  raw_t xr[PPT][C];
+  uint32_t xw[PPT];
+  int npx[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int64_t rem = b.P - (tile0 + j * 64);
+    npx[j] = rem <= 0 ? 0 : (rem >= 64 ? 64 : (int)rem);
+    xw[j] = 0u;
+#pragma unroll
+    for (int c = 0; c < C; ++c) xr[j][c] = 0;
+    if (fr.nframes > 0 && npx[j] > 0) {
+      if constexpr (F32) raw_load<C, F32>(fr.x, pc[j], xr[j]);
+      else xw[j] = u8win_load<C>(static_cast<const uint8_t *>(fr.x), tile0 + j * 64, npx[j], lane);
+    }
+  }
+
+  for (int f = 0; f < fr.nframes; ++f) {
+    float x[PPT][C];
+    const void *xf = frame_ptr<C, F32>(fr.x, fr.stride, f);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if constexpr (F32) raw_to_float<C, F32>(xr[j], x[j]);
+      else u8win_extract<C>(xw[j], static_cast<const uint8_t *>(xf), tile0 + j * 64, lane, x[j]);
+    }
+    {
+      // prefetch the next frame (the last frame is re-read: always in bounds)
+      const void *xf1 = frame_ptr<C, F32>(fr.x, fr.stride, f + 1 < fr.nframes ? f + 1 : f);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (npx[j] > 0) {
+          if constexpr (F32) raw_load<C, F32>(xf1, pc[j], xr[j]);
+          else xw[j] = u8win_load<C>(static_cast<const uint8_t *>(xf1), tile0 + j * 64, npx[j], lane);
+        }
+      }
+    }
+
+    // dense: S0 and S1
+    int st[PPT];
+    bool surv[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int li = j * 64 + lane;
+      st[j] = -1;
+      surv[j] = false;
+      if (valid[j]) {
+        const float dl = frame_delta<C>(x[j], xp[j]);
+        if (fd_on && dl <= kp.tau_fd) {
+          st[j] = 0;
+        } else {
+          float dr2 = 0.0f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const float d = x[j][c] - rmu[j][c];
+            dr2 = dr2 + d * d;
+          }
+          if (rga_on && dr2 <= kp.lam_r2 * rvar[j]) {
+            st[j] = 1;
+            lab[j] = false;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+              rmu[j][c] = kp.one_m_alpha_rga * rmu[j][c] + kp.alpha_rga * x[j][c];
+            float sr = 0.0f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+              const float e = x[j][c] - rmu[j][c];
+              sr = sr + e * e;
+            }
+            const float v = kp.one_m_alpha_rga * rvar[j] + kp.alpha_rga * sr;
+            rvar[j] = v < kp.var_min ? kp.var_min : v;
+            dirty[j] = true;
+          } else {
+            surv[j] = true;
+#pragma unroll
+            for (int c = 0; c < C; ++c) s_x[li * C + c] = x[j][c];
+            s_dl[li] = dl;
+            s_dr2[li] = dr2;
+            s_var[li] = rvar[j];
+          }
+        }
+      }
+    }
+    // list A: S1 survivors in pixel order
+    int nA = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const unsigned long long bal = __ballot(surv[j]);
+      if (surv[j]) s_la[nA + lane_prefix(bal)] = (uint16_t)(j * 64 + lane);
+      nA += (int)__popcll(bal);
+    }
+    wave_sync();
+
+    // S2 over list A, survivors into list B
+    int nB = 0;
+    for (int r0 = 0; r0 < nA; r0 += 64) {
+      const int i = r0 + lane;
+      bool go3 = false;
+      int li = 0;
+      if (i < nA) {
+        li = s_la[i];
+        float conf = 0.0f;
+        bool accept = false;
+        if (kde_on) {
+          const uint8_t *rec = LP ? reinterpret_cast<const uint8_t *>(&s_prior[li * (PB / 16)])
+                                  : b.prior + (tile0 + li) * PB;
+          float xl[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) xl[c] = s_x[li * C + c];
+          conf = confidence<C, F32>(rec, xl, s_dl[li], s_dr2[li], s_var[li], kp);
+          accept = conf >= kp.conf_thr;
+        }
+        if (accept) {
+          s_res[li] = (uint8_t)(2 << 2);
+        } else {
+          go3 = true;
+          s_conf[li] = conf;
+        }
+      }
+      const unsigned long long bal = __ballot(go3);
+      if (go3) s_lb[nB + lane_prefix(bal)] = (uint16_t)li;
+      nB += (int)__popcll(bal);
+    }
+    wave_sync();
+
+    // S3 over list B
+    for (int i = lane; i < nB; i += 64) {
+      const int li = s_lb[i];
+      const int64_t p = tile0 + li;
+      float xx[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) xx[c] = s_x[li * C + c];
+      const float ae = kp.alpha * (1.0f - kp.kappa * s_conf[li]);
+      Mix<C, K> m;
+      rec_load<C, K>(b.gmm + p * R, m);
+      int l, mp;
+      mix_step<C, K>(m, xx, ae, kp, l, mp);
+      rec_store<C, K>(b.gmm + p * R, m);
+      uint8_t res = (uint8_t)((3 << 2) | (l ? 1 : 0));
+      if (!l) {
+        float sm[C], sv = m.var[0];
+#pragma unroll
+        for (int c = 0; c < C; ++c) sm[c] = m.mu[0][c];
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+          if (mp == k) {
+            sv = m.var[k];
+#pragma unroll
+            for (int c = 0; c < C; ++c) sm[c] = m.mu[k][c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_rg[li * (C + 1) + c] = sm[c];
+        s_rg[li * (C + 1) + C] = sv;
+        res |= 2;
+      }
+      s_res[li] = res;
+    }
+    wave_sync();
+
+    // hand-back, mask, level statistics
+    uint8_t *mk = fr.mask ? fr.mask + (int64_t)f * fr.mstride : nullptr;
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c3bg = 0, cfg = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int li = j * 64 + lane;
+      if (surv[j]) {
+        const uint8_t r = s_res[li];
+        lab[j] = (r & 1) != 0;
+        st[j] = r >> 2;
+        if (r & 2) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) rmu[j][c] = s_rg[li * (C + 1) + c];
+          rvar[j] = s_rg[li * (C + 1) + C];
+          dirty[j] = true;
+        }
+      }
+      if (valid[j]) {
+        if (mk) mk[tile0 + li] = lab[j] ? 255 : 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) xp[j][c] = x[j][c];
+      }
+      if (fr.partials) {
+        c0 += (uint32_t)__popcll(__ballot(st[j] == 0));
+        c1 += (uint32_t)__popcll(__ballot(st[j] == 1));
+        c2 += (uint32_t)__popcll(__ballot(st[j] == 2));
+        c3 += (uint32_t)__popcll(__ballot(st[j] == 3));
+        c3bg += (uint32_t)__popcll(__ballot(st[j] == 3 && !lab[j]));
+        cfg += (uint32_t)__popcll(__ballot(valid[j] && lab[j]));
+      }
+    }
+    if (fr.partials && lane < kStat) {
+      const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
+                       : lane == 4 ? c3bg : lane == 5 ? cfg : 0u;
+      fr.partials[((int64_t)f * fr.nslots + blockIdx.x) * kStat + lane] = v;
+    }
+    wave_sync();
+  }
+
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int64_t p = tile0 + j * 64 + lane;
+    if (valid[j]) {
+      if (dirty[j]) {
+        float *rg = b.rga + p * RG;
+#pragma unroll
+        for (int c = 0; c < C; ++c) rg[c] = rmu[j][c];
+        rg[C] = rvar[j];
+      }
+      store_px<C, F32>(b.prev, p, xp[j]);
+    }
+    const unsigned long long bal = __ballot(lab[j]);
+    if (lane == 0 && tile0 + j * 64 < b.P) b.labels[(tile0 + j * 64) >> 6] = bal;
+  }
+}
+
+
+// ============================================================================
+// The cascade with one wave per 64 consecutive pixels and one pixel per lane.
+// A wave never holds more than 64 survivors, so S2 and S3 take one pass
+// whether or not the survivors are compacted; here each survivor stays in its
+// own lane, which removes the list hand-offs from the per-frame critical path
+// and lets the mixture-record load of a survivor start as soon as S1 rejects
+// it, overlapping the S2 arithmetic.  (The compacting kernels above pool the
+// survivors of 128..1024 pixels into dense lists instead.)
+template <int C, int K, bool F32, bool LP>
+__global__ __launch_bounds__(64) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
+  constexpr int R = rec_floats(C, K);
+  constexpr int RG = rga_floats(C);
+  constexpr int PB = prior_bytes(C);
+  using raw_t = typename RawT<F32>::type;
+  __shared__ uint4 s_prior[LP ? 64 * PB / 16 : 1];
+
+  const int lane = threadIdx.x;
+  const int64_t tile0 = (int64_t)blockIdx.x * 64;
+  const int64_t p = tile0 + lane;
+  const bool valid = p < b.P;
+  const int64_t pcl = valid ? p : b.P - 1;
+  const int64_t rem = b.P - tile0;
+  const int npx = rem >= 64 ? 64 : (int)rem;
+  const bool fd_on = (kp.stage_mask & 1u) != 0;
+  const bool rga_on = (kp.stage_mask & 2u) != 0;
+  const bool kde_on = (kp.stage_mask & 4u) != 0;
+
+  float xp[C], rmu[C], rvar = 0.0f;
+  bool lab = false, dirty = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) xp[c] = rmu[c] = 0.0f;
+  if (valid) {
+    lab = ((b.labels[p >> 6] >> lane) & 1ull) != 0;
+    load_px<C, F32>(b.prev, p, xp);
+    const float *rg = b.rga + p * RG;
+#pragma unroll
+    for (int c = 0; c < C; ++c) rmu[c] = rg[c];
+    rvar = rg[C];
+    if constexpr (LP) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(b.prior + p * PB);
+#pragma unroll
+      for (int q = 0; q < PB / 16; ++q) s_prior[lane * (PB / 16) + q] = src[q];
+    }
+  }
+  // a lane reads back only its own staged record, so no wave-level sync is needed
+  const uint8_t *prec = LP ? reinterpret_cast<const uint8_t *>(&s_prior[lane * (PB / 16)])
+                           : b.prior + pcl * PB;
+  float *grec = b.gmm + pcl * R;
+
+  raw_t xr[C];
+  uint32_t xw = 0u;
+#pragma unroll
+  for (int c = 0; c < C; ++c) xr[c] = 0;
+  if (fr.nframes > 0) {
+    if constexpr (F32) raw_load<C, F32>(fr.x, pcl, xr);
+    else xw = u8win_load<C>(static_cast<const uint8_t *>(fr.x), tile0, npx, lane);
+  }
+
+  for (int f = 0; f < fr.nframes; ++f) {
+    float x[C];
+    const void *xf = frame_ptr<C, F32>(fr.x, fr.stride, f);
+    if constexpr (F32) raw_to_float<C, F32>(xr, x);
+    else u8win_extract<C>(xw, static_cast<const uint8_t *>(xf), tile0, lane, x);
+    {
+      const void *xf1 = frame_ptr<C, F32>(fr.x, fr.stride, f + 1 < fr.nframes ? f + 1 : f);
+      if constexpr (F32) raw_load<C, F32>(xf1, pcl, xr);
+      else xw = u8win_load<C>(static_cast<const uint8_t *>(xf1), tile0, npx, lane);
+    }
+
+    int st = -1;
+    if (valid) {
+      const float dl = frame_delta<C>(x, xp);
+      if (fd_on && dl <= kp.tau_fd) {
+        st = 0;  // S0: repeat the previous label
+      } else {
+        float dr2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const float d = x[c] - rmu[c];
+          dr2 = dr2 + d * d;
+        }
+        if (rga_on && dr2 <= kp.lam_r2 * rvar) {
+          st = 1;  // S1: background, the running average adapts
+          lab = false;
+#pragma unroll
+          for (int c = 0; c < C; ++c) rmu[c] = kp.one_m_alpha_rga * rmu[c] + kp.alpha_rga * x[c];
+          float sr = 0.0f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const float e = x[c] - rmu[c];
+            sr = sr + e * e;
+          }
+          const float v = kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr;
+          rvar = v < kp.var_min ? kp.var_min : v;
+          dirty = true;
+        } else {
+          // survivor: the mixture record is requested first, S2 runs while it
+          // is in flight, and the mixture step is committed only if S2 does
+          // not accept the pixel
+          Mix<C, K> m;
+          rec_load<C, K>(grec, m);
+          float conf = 0.0f;
+          bool accept = false;
+          if (kde_on) {
+            conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
+            accept = conf >= kp.conf_thr;
+          }
+          const float ae = kp.alpha * (1.0f - kp.kappa * conf);
+          int l, mp;
+          mix_step<C, K>(m, x, ae, kp, l, mp);
+          if (accept) {
+            st = 2;
+            lab = false;
+          } else {
+            st = 3;
+            rec_store<C, K>(grec, m);
+            lab = l != 0;
+            if (!l) {
+              // background from the mixture: the running average takes the
+              // matched component (the transition update of the active level)
+              float sv = m.var[0];
+#pragma unroll
+              for (int c = 0; c < C; ++c) rmu[c] = m.mu[0][c];
+#pragma unroll
+              for (int k = 1; k < K; ++k) {
+                if (mp == k) {
+                  sv = m.var[k];
+#pragma unroll
+                  for (int c = 0; c < C; ++c) rmu[c] = m.mu[k][c];
+                }
+              }
+              rvar = sv;
+              dirty = true;
+            }
+          }
+        }
+      }
+    }
+    if (valid) {
+      if (fr.mask) fr.mask[(int64_t)f * fr.mstride + p] = lab ? 255 : 0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) xp[c] = x[c];
+    }
+    if (fr.partials) {
+      const uint32_t c0 = (uint32_t)__popcll(__ballot(st == 0));
+      const uint32_t c1 = (uint32_t)__popcll(__ballot(st == 1));
+      const uint32_t c2 = (uint32_t)__popcll(__ballot(st == 2));
+      const uint32_t c3 = (uint32_t)__popcll(__ballot(st == 3));
+      const uint32_t c3bg = (uint32_t)__popcll(__ballot(st == 3 && !lab));
+      const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
+      if (lane < kStat) {
+        const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
+                         : lane == 4 ? c3bg : lane == 5 ? cfg : 0u;
+        fr.partials[((int64_t)f * fr.nslots + blockIdx.x) * kStat + lane] = v;
+      }
+    }
+  }
+
+  if (valid) {
+    if (dirty) {
+      float *rg = b.rga + p * RG;
+#pragma unroll
+      for (int c = 0; c < C; ++c) rg[c] = rmu[c];
+      rg[C] = rvar;
+    }
+    store_px<C, F32>(b.prev, p, xp);
+  }
+  const unsigned long long bal = __ballot(lab);
+  if (lane == 0) b.labels[tile0 >> 6] = bal;
+}
+
 // ============================================================================
 // Plain Stauffer-Grimson baseline: every pixel runs the mixture step every
 // frame (alpha fixed), one pixel per thread, state in registers across the
@@ -761,36 +1333,51 @@ hipError_t launch_train(int C, int K, bool f32in, bool prior, bool aos, const Bu
                         const void *frames, int64_t stride, int n, const KParams &kp,
                         hipStream_t s) {
   const unsigned g = grid_for(b.P, kNT);
-#define COG_TRAIN(KK, CC, FF)                                                                  \
-  hipLaunchKernelGGL((k_train<CC, KK, FF>), dim3(g), dim3(kNT), 0, s, b, frames, stride, n, kp, \
-                     prior ? 1 : 0, aos ? 1 : 0)
-  if (C == 3 && !f32in) { COG_K_CASES(COG_TRAIN, 3, false) }
-  else if (C == 3 && f32in) { COG_K_CASES(COG_TRAIN, 3, true) }
-  else if (C == 1 && !f32in) { COG_K_CASES(COG_TRAIN, 1, false) }
-  else if (C == 1 && f32in) { COG_K_CASES(COG_TRAIN, 1, true) }
+  if (prior != aos) return hipErrorInvalidValue;
+#define COG_TRAIN(KK, CC, FF, PR) \
+  hipLaunchKernelGGL((k_train<CC, KK, FF, PR>), dim3(g), dim3(kNT), 0, s, b, frames, stride, n, kp)
+  if (C == 3 && !f32in) { if (prior) { COG_K_CASES(COG_TRAIN, 3, false, true) } else { COG_K_CASES(COG_TRAIN, 3, false, false) } }
+  else if (C == 3 && f32in) { if (prior) { COG_K_CASES(COG_TRAIN, 3, true, true) } else { COG_K_CASES(COG_TRAIN, 3, true, false) } }
+  else if (C == 1 && !f32in) { if (prior) { COG_K_CASES(COG_TRAIN, 1, false, true) } else { COG_K_CASES(COG_TRAIN, 1, false, false) } }
+  else if (C == 1 && f32in) { if (prior) { COG_K_CASES(COG_TRAIN, 1, true, true) } else { COG_K_CASES(COG_TRAIN, 1, true, false) } }
   else return hipErrorInvalidValue;
 #undef COG_TRAIN
   return hipGetLastError();
 }
 
-hipError_t launch_cascade(int C, int K, bool f32in, int ppt, const Buffers &b, const Frames &fr,
+hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, const Frames &fr,
                           const KParams &kp, hipStream_t s) {
-  const unsigned g = grid_for(b.P, kNT * ppt);
-#define COG_CASC(KK, CC, FF, PP) \
-  hipLaunchKernelGGL((k_cascade<CC, KK, FF, PP>), dim3(g), dim3(kNT), 0, s, b, fr, kp)
-#define COG_CASC_PPT(CC, FF)                                        \
-  switch (ppt) {                                                   \
-    case 1: { COG_K_CASES(COG_CASC, CC, FF, 1) } break;            \
-    case 2: { COG_K_CASES(COG_CASC, CC, FF, 2) } break;            \
-    case 4: { COG_K_CASES(COG_CASC, CC, FF, 4) } break;            \
-    default: return hipErrorInvalidValue;                          \
+  const unsigned g = grid_for(b.P, tile);
+  // the prior goes to LDS when a launch covers enough frames to amortise it
+  const bool lp = fr.nframes >= 8;
+#define COG_CASC(KK, CC, FF, PP, LL) \
+  hipLaunchKernelGGL((k_cascade<CC, KK, FF, PP, LL>), dim3(g), dim3(kNT), 0, s, b, fr, kp)
+#define COG_CASCW(KK, CC, FF, PP, LL) \
+  hipLaunchKernelGGL((k_cascade_w<CC, KK, FF, PP, LL>), dim3(g), dim3(64), 0, s, b, fr, kp)
+#define COG_CASCD(KK, CC, FF, LL) \
+  hipLaunchKernelGGL((k_cascade_d<CC, KK, FF, LL>), dim3(g), dim3(64), 0, s, b, fr, kp)
+#define COG_CASC_TILE(CC, FF)                                                   \
+  switch (tile * 2 + (lp ? 1 : 0)) {                                           \
+    case 128: { COG_K_CASES(COG_CASCD, CC, FF, false) } break;                 \
+    case 129: { COG_K_CASES(COG_CASCD, CC, FF, true) } break;                  \
+    case 256: { COG_K_CASES(COG_CASCW, CC, FF, 2, false) } break;              \
+    case 257: { COG_K_CASES(COG_CASCW, CC, FF, 2, true) } break;               \
+    case 512: { COG_K_CASES(COG_CASC, CC, FF, 1, false) } break;               \
+    case 513: { COG_K_CASES(COG_CASC, CC, FF, 1, true) } break;                \
+    case 1024: { COG_K_CASES(COG_CASC, CC, FF, 2, false) } break;              \
+    case 1025: { COG_K_CASES(COG_CASC, CC, FF, 2, true) } break;               \
+    case 2048: { COG_K_CASES(COG_CASC, CC, FF, 4, false) } break;              \
+    case 2049: { COG_K_CASES(COG_CASC, CC, FF, 4, true) } break;               \
+    default: return hipErrorInvalidValue;                                      \
   }
-  if (C == 3 && !f32in) { COG_CASC_PPT(3, false) }
-  else if (C == 3 && f32in) { COG_CASC_PPT(3, true) }
-  else if (C == 1 && !f32in) { COG_CASC_PPT(1, false) }
-  else if (C == 1 && f32in) { COG_CASC_PPT(1, true) }
+  if (C == 3 && !f32in) { COG_CASC_TILE(3, false) }
+  else if (C == 3 && f32in) { COG_CASC_TILE(3, true) }
+  else if (C == 1 && !f32in) { COG_CASC_TILE(1, false) }
+  else if (C == 1 && f32in) { COG_CASC_TILE(1, true) }
   else return hipErrorInvalidValue;
-#undef COG_CASC_PPT
+#undef COG_CASC_TILE
+#undef COG_CASCW
+#undef COG_CASCD
 #undef COG_CASC
   return hipGetLastError();
 }

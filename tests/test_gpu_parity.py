@@ -74,7 +74,7 @@ def test_multi_frame_launch_equals_per_frame(C):
         assert np.array_equal(s1[k], s2[k]) and np.array_equal(s1[k], s3[k]), k
 
 
-@pytest.mark.parametrize("tile", [256, 512, 1024])
+@pytest.mark.parametrize("tile", [64, 128, 256, 512, 1024])
 def test_tile_size_invariance(C, tile):
     fr = small_stream(w=97, h=61, frames=90, n_train=30)
     p = gpu_params(C, 97, 61, K=3, tile_px=tile)
