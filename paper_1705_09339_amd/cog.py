@@ -60,10 +60,10 @@ class CogError(RuntimeError):
         self.status = status
 
 
-def _load():
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libcog.so is not built ({LIB_PATH}); run paper_1705_09339_amd/build.py")
-    L = ct.CDLL(LIB_PATH)
+def _load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"libcog.so is not built ({path}); run paper_1705_09339_amd/build.py")
+    L = ct.CDLL(path)
     P, V = ct.POINTER, ct.c_void_p
     sig = {
         "cog_default_params": ([P(cog_params), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32], ct.c_int),

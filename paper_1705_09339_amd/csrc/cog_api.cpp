@@ -70,7 +70,7 @@ std::string check_params(const cog_params *p) {
   if (!p) return "params is NULL";
   if (p->struct_size != sizeof(cog_params)) return "params.struct_size mismatch";
   if (p->width <= 0 || p->height <= 0) return "width and height must be positive";
-  if ((int64_t)p->width * p->height > (int64_t)1 << 34) return "frame too large";
+  if ((int64_t)p->width * p->height > ((int64_t)1 << 28)) return "frame too large (at most 2^28 pixels)";
   if (p->channels != 1 && p->channels != 3) return "channels must be 1 or 3";
   if (p->dtype != COG_U8 && p->dtype != COG_F32) return "dtype must be COG_U8 or COG_F32";
   if (p->dtype == COG_F32 && !(p->in_hi > p->in_lo)) return "in_hi must exceed in_lo";
@@ -115,10 +115,10 @@ Plan make_plan(const cog_params *p) {
     pl.ntiles = (int)((pl.P + tile - 1) / tile);
     pl.nslots = pl.ntiles;
   } else {
-    pl.tile = cog::kNT;
+    pl.tile = 64;
     pl.ppt = 1;
-    pl.ntiles = (int)((pl.P + cog::kNT - 1) / cog::kNT);
-    pl.nslots = pl.ntiles * cog::kNW;
+    pl.ntiles = (int)((pl.P + 63) / 64);
+    pl.nslots = pl.ntiles;
   }
   size_t off = 0;
   pl.off_gmm = off;

@@ -326,6 +326,78 @@ __device__ __forceinline__ void u8win_extract(uint32_t raw, const uint8_t *frame
   }
 }
 
+
+// Block-staged input for one wave of 64 consecutive pixels.  The wave's
+// window of a frame is 64*C input values; each lane loads NDW dwords of it
+// (u8: lane i loads dword i of the 4-byte-aligned window, at most 49 dwords;
+// f32: dwords i, i+64, ...).  Every NB frames the windows of the next NB
+// frames are requested into registers and the ones requested a block
+// earlier are copied into an LDS ring, so a frame's input is an LDS read and
+// the global-memory wait is paid once per NB frames, on loads issued NB
+// frames before.  Frames past the end re-read the last frame (in bounds).
+template <int C, bool F32, int NB>
+struct InStage {
+  static constexpr int NDW = F32 ? C : 1;
+  uint32_t r[NB][NDW];
+
+  __device__ __forceinline__ void issue(const void *x, int64_t stride, int nframes, int fb,
+                                        int64_t tile0, int npx, int lane) {
+#pragma unroll
+    for (int kk = 0; kk < NB; ++kk) {
+      const int ff = fb + kk < nframes ? fb + kk : nframes - 1;
+      const void *xf = frame_ptr<C, F32>(x, stride, ff);
+      if constexpr (F32) {
+        const uint32_t *base = reinterpret_cast<const uint32_t *>(xf) + tile0 * C;
+        const int nd = npx * C;
+#pragma unroll
+        for (int d = 0; d < NDW; ++d) {
+          const int i = lane + 64 * d;
+          r[kk][d] = __builtin_nontemporal_load(base + (i < nd ? i : nd - 1));
+        }
+      } else {
+        r[kk][0] = u8win_load<C>(static_cast<const uint8_t *>(xf), tile0, npx, lane);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void commit(uint32_t *s, int lane) const {
+#pragma unroll
+    for (int kk = 0; kk < NB; ++kk)
+#pragma unroll
+      for (int d = 0; d < NDW; ++d) s[(kk * NDW + d) * 64 + lane] = r[kk][d];
+  }
+
+  // value of this lane's pixel in slot k; mis = the frame's run misalignment
+  static __device__ __forceinline__ void read_mis(const uint32_t *s, int k, int mis, int lane,
+                                                  float (&x)[C]) {
+    if constexpr (F32) {
+      const float *fs = reinterpret_cast<const float *>(s + k * NDW * 64);
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = fs[C * lane + c];
+    } else {
+      const uint8_t *bs = reinterpret_cast<const uint8_t *>(s + k * 64);
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = (float)bs[mis + C * lane + c];
+    }
+  }
+
+  // value of this lane's pixel in slot k (frame xf of the ring)
+  static __device__ __forceinline__ void read(const uint32_t *s, int k, const void *xf,
+                                              int64_t tile0, int lane, float (&x)[C]) {
+    if constexpr (F32) {
+      const float *fs = reinterpret_cast<const float *>(s + k * NDW * 64);
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = fs[C * lane + c];
+    } else {
+      const uint8_t *bs = reinterpret_cast<const uint8_t *>(s + k * 64);
+      const int mis =
+          (int)(reinterpret_cast<uintptr_t>(static_cast<const uint8_t *>(xf) + tile0 * C) & 3);
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = (float)bs[mis + C * lane + c];
+    }
+  }
+};
+
 // Compiler-level ordering of LDS accesses between the lanes of one wave (the
 // hardware executes a wave's LDS instructions in order).
 __device__ __forceinline__ void wave_sync() {
@@ -1095,17 +1167,27 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
 // The cascade with one wave per 64 consecutive pixels and one pixel per lane.
 // A wave never holds more than 64 survivors, so S2 and S3 take one pass
 // whether or not the survivors are compacted; here each survivor stays in its
-// own lane, which removes the list hand-offs from the per-frame critical path
-// and lets the mixture-record load of a survivor start as soon as S1 rejects
-// it, overlapping the S2 arithmetic.  (The compacting kernels above pool the
-// survivors of 128..1024 pixels into dense lists instead.)
+// own lane, which keeps list hand-offs off the per-frame critical path.
+// (The compacting kernels above pool the survivors of 128..1024 pixels into
+// dense lists instead.)
+//  - dense state (previous value, label, running average) in registers for
+//    the whole launch;
+//  - a pixel's mixture record is read from HBM the first time the pixel
+//    reaches S3 in the launch (the load is issued before S2 runs) and then
+//    stays in registers -- only this lane ever touches it -- and is written
+//    back once at the end of the launch;
+//  - the input is block-staged through LDS (InStage): the global-memory wait
+//    is paid once per block of frames, on loads issued a block earlier;
+//  - the mask and statistics stores are bounds-checked buffer stores.
 template <int C, int K, bool F32, bool LP>
 __global__ __launch_bounds__(64) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
   constexpr int R = rec_floats(C, K);
   constexpr int RG = rga_floats(C);
   constexpr int PB = prior_bytes(C);
-  using raw_t = typename RawT<F32>::type;
+  constexpr int NB = 8;  // frames per input block
+  using Stage = InStage<C, F32, NB>;
   __shared__ uint4 s_prior[LP ? 64 * PB / 16 : 1];
+  __shared__ uint32_t s_in[NB * Stage::NDW * 64];
 
   const int lane = threadIdx.x;
   const int64_t tile0 = (int64_t)blockIdx.x * 64;
@@ -1119,11 +1201,13 @@ __global__ __launch_bounds__(64) void k_cascade_d(Buffers b, Frames fr, KParams 
   const bool kde_on = (kp.stage_mask & 4u) != 0;
 
   float xp[C], rmu[C], rvar = 0.0f;
-  bool lab = false, dirty = false;
+  // per-lane flags kept as integers (0/1) so that branch joins cost no
+  // lane-mask bookkeeping
+  uint32_t lab = 0u, dirty = 0u, have_rec = 0u, rec_dirty = 0u;
 #pragma unroll
   for (int c = 0; c < C; ++c) xp[c] = rmu[c] = 0.0f;
   if (valid) {
-    lab = ((b.labels[p >> 6] >> lane) & 1ull) != 0;
+    lab = (uint32_t)((b.labels[p >> 6] >> lane) & 1ull);
     load_px<C, F32>(b.prev, p, xp);
     const float *rg = b.rga + p * RG;
 #pragma unroll
@@ -1139,117 +1223,135 @@ __global__ __launch_bounds__(64) void k_cascade_d(Buffers b, Frames fr, KParams 
   const uint8_t *prec = LP ? reinterpret_cast<const uint8_t *>(&s_prior[lane * (PB / 16)])
                            : b.prior + pcl * PB;
   float *grec = b.gmm + pcl * R;
+  Mix<C, K> m;  // the pixel's mixture, valid once have_rec
 
-  raw_t xr[C];
-  uint32_t xw = 0u;
+  // byte offset of the lane's pixel in a frame's mask, and of the lane's
+  // statistics word in a frame's row; out-of-range lanes are dropped by the
+  // buffer stores' bounds check
+  const int moff = valid ? (int)p : 0x7fffffff;
+  const int soff = lane < kStat ? (int)((int64_t)blockIdx.x * kStat + lane) * 4 : 0x7fffffff;
+  const int srow = fr.nslots * kStat * 4;  // bytes per statistics row
+
+  // misalignment of the tile's input run within 4 bytes, frame by frame
+  const int in_bytes = F32 ? 4 : 1;
+  const int mis0 = (int)((reinterpret_cast<uintptr_t>(fr.x) + (uint64_t)tile0 * C * in_bytes) & 3);
+  const int mis_step = (int)(((uint64_t)fr.stride * in_bytes) & 3);
+
+  Stage in;
+  if (fr.nframes > 0) in.issue(fr.x, fr.stride, fr.nframes, 0, tile0, npx, lane);
+
+  for (int f0 = 0; f0 < fr.nframes; f0 += NB) {
+    in.commit(s_in, lane);
+    wave_sync();
+    in.issue(fr.x, fr.stride, fr.nframes, f0 + NB, tile0, npx, lane);
+    const int nk = fr.nframes - f0 < NB ? fr.nframes - f0 : NB;
+    // this block's masks and statistics rows (frame k at soffset k * row)
+    const __amdgpu_buffer_rsrc_t mr = __builtin_amdgcn_make_buffer_rsrc(
+        fr.mask ? fr.mask + (int64_t)f0 * fr.mstride : nullptr, (short)0,
+        fr.mask ? (int)(nk * fr.mstride) : 0, 0x00020000);
+    const __amdgpu_buffer_rsrc_t sr = __builtin_amdgcn_make_buffer_rsrc(
+        fr.partials ? fr.partials + (int64_t)f0 * fr.nslots * kStat : nullptr, (short)0,
+        fr.partials ? nk * srow : 0, 0x00020000);
+    int mis = (mis0 + f0 * mis_step) & 3;
+
+    for (int k = 0; k < nk; ++k, mis = (mis + mis_step) & 3) {
+      float x[C];
+      Stage::read_mis(s_in, k, mis, lane, x);
+
+      // S0 (frame difference) and S1 (running average) for every lane
+      float dl = 0.0f;
 #pragma unroll
-  for (int c = 0; c < C; ++c) xr[c] = 0;
-  if (fr.nframes > 0) {
-    if constexpr (F32) raw_load<C, F32>(fr.x, pcl, xr);
-    else xw = u8win_load<C>(static_cast<const uint8_t *>(fr.x), tile0, npx, lane);
-  }
-
-  for (int f = 0; f < fr.nframes; ++f) {
-    float x[C];
-    const void *xf = frame_ptr<C, F32>(fr.x, fr.stride, f);
-    if constexpr (F32) raw_to_float<C, F32>(xr, x);
-    else u8win_extract<C>(xw, static_cast<const uint8_t *>(xf), tile0, lane, x);
-    {
-      const void *xf1 = frame_ptr<C, F32>(fr.x, fr.stride, f + 1 < fr.nframes ? f + 1 : f);
-      if constexpr (F32) raw_load<C, F32>(xf1, pcl, xr);
-      else xw = u8win_load<C>(static_cast<const uint8_t *>(xf1), tile0, npx, lane);
-    }
-
-    int st = -1;
-    if (valid) {
-      const float dl = frame_delta<C>(x, xp);
-      if (fd_on && dl <= kp.tau_fd) {
-        st = 0;  // S0: repeat the previous label
-      } else {
-        float dr2 = 0.0f;
+      for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xp[c]));
+      float dr2 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float d = x[c] - rmu[c];
+        dr2 = dr2 + d * d;
+      }
+      const bool s0 = fd_on && dl <= kp.tau_fd;
+      const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * rvar;
+      {
+        float nmu[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) nmu[c] = kp.one_m_alpha_rga * rmu[c] + kp.alpha_rga * x[c];
+        float sr = 0.0f;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const float d = x[c] - rmu[c];
-          dr2 = dr2 + d * d;
+          const float e = x[c] - nmu[c];
+          sr = sr + e * e;
         }
-        if (rga_on && dr2 <= kp.lam_r2 * rvar) {
-          st = 1;  // S1: background, the running average adapts
-          lab = false;
+        const float nvar = fmaxf(kp.var_min, kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr);
 #pragma unroll
-          for (int c = 0; c < C; ++c) rmu[c] = kp.one_m_alpha_rga * rmu[c] + kp.alpha_rga * x[c];
-          float sr = 0.0f;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const float e = x[c] - rmu[c];
-            sr = sr + e * e;
-          }
-          const float v = kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr;
-          rvar = v < kp.var_min ? kp.var_min : v;
-          dirty = true;
-        } else {
-          // survivor: the mixture record is requested first, S2 runs while it
-          // is in flight, and the mixture step is committed only if S2 does
-          // not accept the pixel
-          Mix<C, K> m;
+        for (int c = 0; c < C; ++c) rmu[c] = s1 ? nmu[c] : rmu[c];
+        rvar = s1 ? nvar : rvar;
+      }
+      dirty |= s1 ? 1u : 0u;
+      lab = s1 ? 0u : lab;
+      int st = !valid ? -1 : (s0 ? 0 : (s1 ? 1 : 3));
+
+      if (valid && !s0 && !s1) {
+        // survivor: first time in this launch, the mixture record is
+        // requested before S2 runs
+        if (!have_rec) {
           rec_load<C, K>(grec, m);
-          float conf = 0.0f;
-          bool accept = false;
-          if (kde_on) {
-            conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
-            accept = conf >= kp.conf_thr;
-          }
+          have_rec = 1u;
+        }
+        float conf = 0.0f;
+        bool accept = false;
+        if (kde_on) {
+          conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
+          accept = conf >= kp.conf_thr;
+        }
+        if (accept) {
+          st = 2;  // S2: background by the scene prior, nothing adapts
+          lab = 0u;
+        } else {
+          // S3: the full mixture with the confidence-driven rate
           const float ae = kp.alpha * (1.0f - kp.kappa * conf);
           int l, mp;
           mix_step<C, K>(m, x, ae, kp, l, mp);
-          if (accept) {
-            st = 2;
-            lab = false;
-          } else {
-            st = 3;
-            rec_store<C, K>(grec, m);
-            lab = l != 0;
-            if (!l) {
-              // background from the mixture: the running average takes the
-              // matched component (the transition update of the active level)
-              float sv = m.var[0];
+          rec_dirty = 1u;
+          lab = l ? 1u : 0u;
+          if (!l) {
+            // background from the mixture: the running average takes the
+            // matched component (the transition update of the active level)
+            float sv = m.var[0];
 #pragma unroll
-              for (int c = 0; c < C; ++c) rmu[c] = m.mu[0][c];
+            for (int c = 0; c < C; ++c) rmu[c] = m.mu[0][c];
 #pragma unroll
-              for (int k = 1; k < K; ++k) {
-                if (mp == k) {
-                  sv = m.var[k];
+            for (int kk = 1; kk < K; ++kk) {
+              if (mp == kk) {
+                sv = m.var[kk];
 #pragma unroll
-                  for (int c = 0; c < C; ++c) rmu[c] = m.mu[k][c];
-                }
+                for (int c = 0; c < C; ++c) rmu[c] = m.mu[kk][c];
               }
-              rvar = sv;
-              dirty = true;
             }
+            rvar = sv;
+            dirty = 1u;
           }
         }
       }
-    }
-    if (valid) {
-      if (fr.mask) fr.mask[(int64_t)f * fr.mstride + p] = lab ? 255 : 0;
 #pragma unroll
       for (int c = 0; c < C; ++c) xp[c] = x[c];
-    }
-    if (fr.partials) {
-      const uint32_t c0 = (uint32_t)__popcll(__ballot(st == 0));
-      const uint32_t c1 = (uint32_t)__popcll(__ballot(st == 1));
-      const uint32_t c2 = (uint32_t)__popcll(__ballot(st == 2));
-      const uint32_t c3 = (uint32_t)__popcll(__ballot(st == 3));
-      const uint32_t c3bg = (uint32_t)__popcll(__ballot(st == 3 && !lab));
-      const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
-      if (lane < kStat) {
+      __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(lab ? 255 : 0), mr, moff,
+                                           k * (int)fr.mstride, 0);
+      if (fr.partials) {
+        const uint32_t c0 = (uint32_t)__popcll(__ballot(st == 0));
+        const uint32_t c1 = (uint32_t)__popcll(__ballot(st == 1));
+        const uint32_t c2 = (uint32_t)__popcll(__ballot(st == 2));
+        const uint32_t c3 = (uint32_t)__popcll(__ballot(st == 3));
+        const uint32_t c3bg = (uint32_t)__popcll(__ballot(st == 3 && !lab));
+        const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
         const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
                          : lane == 4 ? c3bg : lane == 5 ? cfg : 0u;
-        fr.partials[((int64_t)f * fr.nslots + blockIdx.x) * kStat + lane] = v;
+        __builtin_amdgcn_raw_buffer_store_b32(v, sr, soff, k * srow, 0);
       }
     }
+    wave_sync();
   }
 
   if (valid) {
+    if (rec_dirty) rec_store<C, K>(grec, m);
     if (dirty) {
       float *rg = b.rga + p * RG;
 #pragma unroll
@@ -1258,57 +1360,66 @@ __global__ __launch_bounds__(64) void k_cascade_d(Buffers b, Frames fr, KParams 
     }
     store_px<C, F32>(b.prev, p, xp);
   }
-  const unsigned long long bal = __ballot(lab);
+  const unsigned long long bal = __ballot(valid && lab);
   if (lane == 0) b.labels[tile0 >> 6] = bal;
 }
 
 // ============================================================================
 // Plain Stauffer-Grimson baseline: every pixel runs the mixture step every
-// frame (alpha fixed), one pixel per thread, state in registers across the
-// frames of the launch, 64-pixel field-major record groups.
+// frame (alpha fixed), one wave per 64 pixels and one pixel per lane, the
+// mixture in registers across the frames of the launch, 64-pixel field-major
+// record groups, and the same block-staged input as the cascade.
 template <int C, int K, bool F32>
-__global__ __launch_bounds__(kNT) void k_gmm(Buffers b, Frames fr, KParams kp) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+__global__ __launch_bounds__(64) void k_gmm(Buffers b, Frames fr, KParams kp) {
+  const int lane = threadIdx.x;
+  const int64_t tile0 = (int64_t)blockIdx.x * 64;
+  const int64_t p = tile0 + lane;
   const bool valid = p < b.P;
+  const int64_t rem = b.P - tile0;
+  const int npx = rem >= 64 ? 64 : (int)rem;
   Mix<C, K> m;
   float x[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) x[c] = 0.0f;
   if (valid) grp_load<C, K>(b.gmm, p, m);
   bool lab = false;
-  for (int f = 0; f < fr.nframes; ++f) {
-    if (valid) {
-      load_px<C, F32>(frame_ptr<C, F32>(fr.x, fr.stride, f), p, x);
-      int l, mp;
-      mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
-      lab = l != 0;
-      if (fr.mask) fr.mask[(int64_t)f * fr.mstride + p] = lab ? 255 : 0;
-    }
-    if (fr.partials) {
-      const uint32_t nv = (uint32_t)__popcll(__ballot(valid));
-      const uint32_t nf = (uint32_t)__popcll(__ballot(valid && lab));
-      if (lane == 0) {
-        uint32_t *dst =
-            fr.partials + ((int64_t)f * fr.nslots + (int64_t)blockIdx.x * kNW + wave) * kStat;
-        dst[0] = 0u;
-        dst[1] = 0u;
-        dst[2] = 0u;
-        dst[3] = nv;
-        dst[4] = nv - nf;
-        dst[5] = nf;
-        dst[6] = 0u;
-        dst[7] = 0u;
+
+  constexpr int NB = 8;
+  using Stage = InStage<C, F32, NB>;
+  __shared__ uint32_t s_in[NB * Stage::NDW * 64];
+  Stage in;
+  if (fr.nframes > 0) in.issue(fr.x, fr.stride, fr.nframes, 0, tile0, npx, lane);
+  for (int f0 = 0; f0 < fr.nframes; f0 += NB) {
+    in.commit(s_in, lane);
+    wave_sync();
+    in.issue(fr.x, fr.stride, fr.nframes, f0 + NB, tile0, npx, lane);
+    const int nk = fr.nframes - f0 < NB ? fr.nframes - f0 : NB;
+    for (int k = 0; k < nk; ++k) {
+      const int f = f0 + k;
+      Stage::read(s_in, k, frame_ptr<C, F32>(fr.x, fr.stride, f), tile0, lane, x);
+      if (valid) {
+        int l, mp;
+        mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
+        lab = l != 0;
+        if (fr.mask) fr.mask[(int64_t)f * fr.mstride + p] = lab ? 255 : 0;
+      }
+      if (fr.partials) {
+        const uint32_t nv = (uint32_t)__popcll(__ballot(valid));
+        const uint32_t nf = (uint32_t)__popcll(__ballot(valid && lab));
+        if (lane < kStat) {
+          const uint32_t v = lane == 3 ? nv : lane == 4 ? nv - nf : lane == 5 ? nf : 0u;
+          fr.partials[((int64_t)f * fr.nslots + blockIdx.x) * kStat + lane] = v;
+        }
       }
     }
+    wave_sync();
   }
   if (valid) {
     grp_store<C, K>(b.gmm, p, m);
     if (fr.nframes > 0) store_px<C, F32>(b.prev, p, x);
   }
   const unsigned long long bal = __ballot(lab);
-  const int64_t w0 = p - lane;
-  if (fr.nframes > 0 && lane == 0 && w0 < b.P) b.labels[w0 >> 6] = bal;
+  if (fr.nframes > 0 && lane == 0) b.labels[tile0 >> 6] = bal;
 }
 
 }  // namespace
@@ -1384,9 +1495,9 @@ hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, 
 
 hipError_t launch_gmm(int C, int K, bool f32in, const Buffers &b, const Frames &fr,
                       const KParams &kp, hipStream_t s) {
-  const unsigned g = grid_for(b.P, kNT);
+  const unsigned g = grid_for(b.P, 64);
 #define COG_GMM(KK, CC, FF) \
-  hipLaunchKernelGGL((k_gmm<CC, KK, FF>), dim3(g), dim3(kNT), 0, s, b, fr, kp)
+  hipLaunchKernelGGL((k_gmm<CC, KK, FF>), dim3(g), dim3(64), 0, s, b, fr, kp)
   if (C == 3 && !f32in) { COG_K_CASES(COG_GMM, 3, false) }
   else if (C == 3 && f32in) { COG_K_CASES(COG_GMM, 3, true) }
   else if (C == 1 && !f32in) { COG_K_CASES(COG_GMM, 1, false) }
