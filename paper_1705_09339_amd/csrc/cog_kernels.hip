@@ -126,31 +126,40 @@ __device__ __forceinline__ void mix_step(Mix<C, K> &s, const float (&x)[C], floa
 #pragma unroll
   for (int k = 0; k < K; ++k) s.w[k] = s.w[k] / S;
 
-  // Insertion sort written as a fixed compare-exchange sequence: inside the
-  // already ranked prefix no pair ranks out of order (the key comparison is
-  // antisymmetric), so the extra comparisons never exchange and the result
-  // equals the early-exit insertion sort.
+  // Re-rank by w/sigma: stable insertion sort.  If no adjacent pair is out of
+  // order the insertion sort exchanges nothing (every pass stops at its first
+  // comparison), so the exchange network runs only in lanes with an adjacent
+  // inversion.  The network itself is the insertion sort written as a fixed
+  // compare-exchange sequence: inside the already ranked prefix no pair ranks
+  // out of order (the key comparison is antisymmetric), so the extra
+  // comparisons never exchange and the result equals the early-exit sort.
   int mp = m;
+  bool inverted = false;
 #pragma unroll
-  for (int i = 1; i < K; ++i) {
+  for (int j = 1; j < K; ++j)
+    inverted |= (s.w[j] * s.w[j]) * s.var[j - 1] > (s.w[j - 1] * s.w[j - 1]) * s.var[j];
+  if (inverted) {
 #pragma unroll
-    for (int j = i; j > 0; --j) {
-      const float lhs = (s.w[j] * s.w[j]) * s.var[j - 1];
-      const float rhs = (s.w[j - 1] * s.w[j - 1]) * s.var[j];
-      if (lhs > rhs) {
-        float t = s.w[j];
-        s.w[j] = s.w[j - 1];
-        s.w[j - 1] = t;
-        t = s.var[j];
-        s.var[j] = s.var[j - 1];
-        s.var[j - 1] = t;
+    for (int i = 1; i < K; ++i) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          t = s.mu[j][c];
-          s.mu[j][c] = s.mu[j - 1][c];
-          s.mu[j - 1][c] = t;
+      for (int j = i; j > 0; --j) {
+        const float lhs = (s.w[j] * s.w[j]) * s.var[j - 1];
+        const float rhs = (s.w[j - 1] * s.w[j - 1]) * s.var[j];
+        if (lhs > rhs) {
+          float t = s.w[j];
+          s.w[j] = s.w[j - 1];
+          s.w[j - 1] = t;
+          t = s.var[j];
+          s.var[j] = s.var[j - 1];
+          s.var[j - 1] = t;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            t = s.mu[j][c];
+            s.mu[j][c] = s.mu[j - 1][c];
+            s.mu[j - 1][c] = t;
+          }
+          mp = (mp == j) ? j - 1 : ((mp == j - 1) ? j : mp);
         }
-        mp = (mp == j) ? j - 1 : ((mp == j - 1) ? j : mp);
       }
     }
   }
@@ -1178,9 +1187,11 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
 //    back once at the end of the launch;
 //  - the input is block-staged through LDS (InStage): the global-memory wait
 //    is paid once per block of frames, on loads issued a block earlier;
-//  - the mask and statistics stores are bounds-checked buffer stores.
+//  - the mask and statistics stores are bounds-checked buffer stores;
+//  - for u8 input up to K = 5 the register budget keeps five waves per SIMD (a 640x480
+//    frame is 4.7 waves per SIMD: all of them stay resident).
 template <int C, int K, bool F32, bool LP>
-__global__ __launch_bounds__(64) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
+__global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
   constexpr int R = rec_floats(C, K);
   constexpr int RG = rga_floats(C);
   constexpr int PB = prior_bytes(C);
