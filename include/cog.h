@@ -169,6 +169,72 @@ cog_status cog_kde_weights(float h, uint16_t *out);
 /* Message of the last failure on h (or of the calling thread if h is NULL). */
 const char *cog_last_error(const cog_ctx *h);
 
+/* ---- Batched tick -----------------------------------------------------------
+ * Many streams advanced together: every pixel of every stream is independent
+ * (§2, "Cascade of Gaussians CoG": the cascade is a per-pixel decision
+ * list), so the 64-pixel tiles of all streams of one tick form a single work
+ * list.  A tick runs one persistent launch per class of streams (channels,
+ * K, input type), replayed from a captured hipGraph, on the batch's stream.
+ * For every item the result (masks, statistics, state) is bit-identical to
+ * cog_step_frames() on that stream alone.
+ *
+ * Ownership: the batch owns its descriptor buffers, graphs and tuning
+ * scratch; it borrows the contexts and the frame/mask buffers of a tick until
+ * the tick's work on the stream completes.  A context may take part in ticks
+ * of one batch and in one-stream calls, in any order, as long as it was
+ * created on the batch's stream. */
+typedef struct cog_batch cog_batch;
+
+/* One stream's work in a tick. */
+typedef struct {
+  cog_ctx *ctx;           /* trained context, cascade path, 64-pixel tiles (tile_px 0 or 64) */
+  const void *frames;     /* device: nframes x H x W x C, contiguous */
+  uint8_t *masks;         /* device: nframes x H x W, or NULL */
+  int32_t nframes;        /* >= 0 (0: the item is skipped); <= 64 when infos is set */
+  int32_t reserved;       /* must be 0 */
+  cog_step_info *infos;   /* host array of nframes entries, or NULL */
+} cog_tick_item;
+
+/* How a class's tiles are spread over the GPU. */
+typedef struct {
+  int32_t blocks_per_cu;  /* persistent workgroups per compute unit; 0: the occupancy limit;
+                             -1: no persistence, one workgroup per schedule unit */
+  int32_t dynamic;        /* 0: units dealt round-robin; 1: taken from an atomic counter */
+  int32_t group;          /* 64-pixel tiles per schedule unit, 1..1024 */
+  int32_t use_graph;      /* 1: replay a captured hipGraph; 0: launch directly */
+} cog_schedule;
+
+/* Create a batch on hip_stream (NULL: default stream) for up to max_items
+ * items per tick (1..4096).  Errors: COG_E_INVALID, COG_E_OOM, COG_E_DEVICE. */
+cog_status cog_batch_create(void *hip_stream, int32_t max_items, cog_batch **out);
+
+/* Advance every item's stream by its nframes frames.  Stream-ordered and
+ * non-blocking unless an item has infos (then the call waits and fills
+ * them).  Errors (nothing runs): COG_E_INVALID (NULL or duplicate context,
+ * context on another stream, bad counts, more than 8 classes),
+ * COG_E_STATE (untrained context), COG_E_UNSUPPORTED (baseline path or
+ * tiles other than 64 pixels), COG_E_DEVICE. */
+cog_status cog_batch_tick(cog_batch *b, const cog_tick_item *items, int32_t n);
+
+/* Time candidate schedules on this tick's work (reps ticks each) and keep
+ * the fastest per class.  Every context's state is restored after each
+ * trial, so the streams are left as they were; the masks of the items are
+ * written (with the tick's result) and no infos are filled.  best (may be
+ * NULL) receives the schedule kept for the first item's class.  Needs
+ * device scratch equal to the items' state bytes.  Errors as for a tick. */
+cog_status cog_batch_autotune(cog_batch *b, const cog_tick_item *items, int32_t n, int32_t reps,
+                              cog_schedule *best);
+
+/* Set or read the schedule of one class (channels, K, dtype).  Classes
+ * without a set schedule use {0, 0, 1, 1}.  COG_E_INVALID for bad values. */
+cog_status cog_batch_set_schedule(cog_batch *b, int32_t channels, int32_t K, int32_t dtype,
+                                  const cog_schedule *s);
+cog_status cog_batch_get_schedule(cog_batch *b, int32_t channels, int32_t K, int32_t dtype,
+                                  cog_schedule *s);
+
+/* Destroy a batch; NULL-safe.  Waits for its stream.  The contexts stay. */
+void cog_batch_destroy(cog_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

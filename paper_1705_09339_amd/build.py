@@ -12,8 +12,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcog.so")
-SOURCES = [os.path.join(CSRC, "cog_kernels.hip"), os.path.join(CSRC, "cog_api.cpp")]
-HEADERS = [os.path.join(CSRC, "cog_device.h"), os.path.join(ROOT, "include", "cog.h")]
+SOURCES = [os.path.join(CSRC, "cog_kernels.hip"), os.path.join(CSRC, "cog_api.cpp"),
+           os.path.join(CSRC, "cog_batch.cpp")]
+HEADERS = [os.path.join(CSRC, "cog_device.h"), os.path.join(CSRC, "cog_ctx.h"),
+           os.path.join(ROOT, "include", "cog.h")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -54,6 +54,23 @@ class cog_step_info(ct.Structure):
                     n3=self.n_stage[3], n3_bg=self.n3_bg, n_fg=self.n_fg, illum_flag=self.illum_flag)
 
 
+class cog_tick_item(ct.Structure):
+    _fields_ = [
+        ("ctx", ct.c_void_p), ("frames", ct.c_void_p), ("masks", ct.c_void_p),
+        ("nframes", ct.c_int32), ("reserved", ct.c_int32), ("infos", ct.c_void_p),
+    ]
+
+
+class cog_schedule(ct.Structure):
+    _fields_ = [
+        ("blocks_per_cu", ct.c_int32), ("dynamic", ct.c_int32), ("group", ct.c_int32),
+        ("use_graph", ct.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class CogError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -79,6 +96,12 @@ def _load(path: str = LIB_PATH):
         "cog_import_state": ([V, V, ct.c_size_t], ct.c_int),
         "cog_kde_weights": ([ct.c_float, P(ct.c_uint16)], ct.c_int),
         "cog_last_error": ([V], ct.c_char_p),
+        "cog_batch_create": ([V, ct.c_int32, P(V)], ct.c_int),
+        "cog_batch_tick": ([V, P(cog_tick_item), ct.c_int32], ct.c_int),
+        "cog_batch_autotune": ([V, P(cog_tick_item), ct.c_int32, ct.c_int32, P(cog_schedule)], ct.c_int),
+        "cog_batch_set_schedule": ([V, ct.c_int32, ct.c_int32, ct.c_int32, P(cog_schedule)], ct.c_int),
+        "cog_batch_get_schedule": ([V, ct.c_int32, ct.c_int32, ct.c_int32, P(cog_schedule)], ct.c_int),
+        "cog_batch_destroy": ([V], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -91,7 +114,9 @@ lib = _load()
 
 EXPORTED = ("cog_default_params", "cog_state_bytes", "cog_canonical_bytes", "cog_create",
             "cog_train_prior", "cog_step", "cog_step_frames", "cog_reset", "cog_destroy",
-            "cog_export_state", "cog_import_state", "cog_kde_weights", "cog_last_error")
+            "cog_export_state", "cog_import_state", "cog_kde_weights", "cog_last_error",
+            "cog_batch_create", "cog_batch_tick", "cog_batch_autotune", "cog_batch_set_schedule",
+            "cog_batch_get_schedule", "cog_batch_destroy")
 
 
 def _check(rc: int, h=None):
@@ -245,6 +270,114 @@ class CogStream:
         if self.h:
             cog_destroy(self.h)
             self.h = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---- batched tick ----------------------------------------------------------------
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def cog_batch_create(stream=None, max_items: int = 256) -> int:
+    b = ct.c_void_p(0)
+    _check(lib.cog_batch_create(_stream_ptr(stream), max_items, ct.byref(b)))
+    return b.value
+
+
+def _items(entries):
+    """entries: (ctx handle, frames, masks or None, nframes or None, want_info)."""
+    n = len(entries)
+    arr = (cog_tick_item * max(n, 1))()
+    keep, infos = [], []
+    for i, (h, frames, masks, nframes, want_info) in enumerate(entries):
+        fp, fdev, k1 = _ptr(frames)
+        mp, mdev, k2 = _ptr(masks)
+        if frames is not None and not fdev:
+            raise ValueError("batched ticks take device frames")
+        if masks is not None and not mdev:
+            raise ValueError("batched ticks take device masks")
+        nf = len(frames) if nframes is None else int(nframes)
+        inf = (cog_step_info * max(nf, 1))() if want_info else None
+        arr[i].ctx = h
+        arr[i].frames = fp
+        arr[i].masks = mp
+        arr[i].nframes = nf
+        arr[i].reserved = 0
+        arr[i].infos = ct.cast(inf, ct.c_void_p) if inf is not None else None
+        keep += [k1, k2, inf]
+        infos.append((inf, nf))
+    return arr, n, keep, infos
+
+
+def cog_batch_tick(b: int, entries):
+    """Advance each entry's stream; returns per entry a list of info dicts (or None)."""
+    arr, n, keep, infos = _items(entries)
+    _check(lib.cog_batch_tick(b, arr, n))
+    del keep
+    return [[inf[i].as_dict() for i in range(nf)] if inf is not None else None
+            for inf, nf in infos]
+
+
+def cog_batch_autotune(b: int, entries, reps: int = 3) -> dict:
+    arr, n, keep, _ = _items(entries)
+    best = cog_schedule()
+    _check(lib.cog_batch_autotune(b, arr, n, reps, ct.byref(best)))
+    del keep
+    return best.as_dict()
+
+
+def cog_batch_set_schedule(b: int, channels: int, K: int, dtype: int, **kw) -> None:
+    s = cog_schedule(blocks_per_cu=kw.get("blocks_per_cu", 0), dynamic=kw.get("dynamic", 0),
+                     group=kw.get("group", 1), use_graph=kw.get("use_graph", 1))
+    _check(lib.cog_batch_set_schedule(b, channels, K, dtype, ct.byref(s)))
+
+
+def cog_batch_get_schedule(b: int, channels: int, K: int, dtype: int) -> dict:
+    s = cog_schedule()
+    _check(lib.cog_batch_get_schedule(b, channels, K, dtype, ct.byref(s)))
+    return s.as_dict()
+
+
+def cog_batch_destroy(b: int) -> None:
+    lib.cog_batch_destroy(b)
+
+
+class CogBatch:
+    """A batch executor on one HIP stream; forwards to the C calls."""
+
+    def __init__(self, stream=None, max_items: int = 256):
+        self.b = cog_batch_create(stream, max_items)
+
+    def tick(self, entries):
+        return cog_batch_tick(self.b, entries)
+
+    def autotune(self, entries, reps: int = 3) -> dict:
+        return cog_batch_autotune(self.b, entries, reps)
+
+    def set_schedule(self, channels, K, dtype, **kw):
+        cog_batch_set_schedule(self.b, channels, K, dtype, **kw)
+
+    def get_schedule(self, channels, K, dtype) -> dict:
+        return cog_batch_get_schedule(self.b, channels, K, dtype)
+
+    def close(self):
+        if self.b:
+            cog_batch_destroy(self.b)
+            self.b = 0
 
     def __del__(self):
         try:

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "cog_ctx.h"
 #include "cog_device.h"
 
 namespace {
@@ -18,42 +19,15 @@ namespace {
 thread_local std::string g_err;
 
 constexpr uint32_t kMagic = 0x31474F43u;  // "COG1"
-constexpr int kChunk = 64;                // frames per launch when statistics are requested
+using cog_rt::kChunk;
+using cog_rt::Plan;
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 size_t pad64(size_t n) { return (n + 63) & ~(size_t)63; }
 
-// Device layout of one stream's state (all regions 256-byte aligned).
-struct Plan {
-  int64_t P = 0, Ppad = 0;
-  int C = 0, K = 0, R = 0, RG = 0, PB = 0, sin = 1;
-  int tile = 0, ppt = 1, ntiles = 0, nslots = 0;
-  size_t off_gmm = 0, off_rga = 0, off_prior = 0, off_cnt = 0, off_prev = 0, off_labels = 0,
-         off_kdew = 0, off_partials = 0, total = 0;
-};
-
 }  // namespace
 
-struct cog_ctx {
-  cog_params p{};
-  Plan plan;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  bool own_state = false;
-  char *dstate = nullptr;
-  cog::Buffers buf{};
-  cog::KParams kp{};
-  int32_t n_train = 0;
-  int64_t frame = 0;
-  void *stage_in = nullptr;
-  size_t stage_in_cap = 0;
-  uint8_t *stage_mask = nullptr;
-  size_t stage_mask_cap = 0;
-  std::vector<uint32_t> host_partials;
-  std::string err;
-};
-
-namespace {
+namespace cog_rt {
 
 cog_status fail(cog_ctx *h, cog_status s, const std::string &msg) {
   if (h) h->err = msg;
@@ -64,6 +38,31 @@ cog_status fail(cog_ctx *h, cog_status s, const std::string &msg) {
 cog_status hip_fail(cog_ctx *h, hipError_t e, const char *what) {
   return fail(h, COG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+void fill_infos(const cog_ctx *h, int64_t first_frame, int n, const uint32_t *blocks,
+                cog_step_info *infos) {
+  const int nb = h->plan.nblk;
+  for (int f = 0; f < n; ++f) {
+    int64_t s[cog::kStat] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t *row = blocks + (size_t)f * nb * cog::kStat;
+    for (int i = 0; i < nb; ++i)
+      for (int k = 0; k < cog::kStat; ++k) s[k] += row[(size_t)i * cog::kStat + k];
+    cog_step_info &o = infos[f];
+    o.frame = first_frame + f;
+    for (int k = 0; k < 4; ++k) o.n_stage[k] = s[k];
+    o.n3_bg = s[4];
+    o.n_fg = s[5];
+    o.illum_flag = ((double)s[3] > (double)h->p.illum_frac * (double)h->plan.P) ? 1 : 0;
+    o.reserved = 0;
+  }
+}
+
+}  // namespace cog_rt
+
+using cog_rt::fail;
+using cog_rt::hip_fail;
+
+namespace {
 
 // Validation of the parameter block; returns an empty string when valid.
 std::string check_params(const cog_params *p) {
@@ -137,6 +136,9 @@ Plan make_plan(const cog_params *p) {
   off += align256(256 * 16 * 2);
   pl.off_partials = off;
   off += align256((size_t)kChunk * pl.nslots * cog::kStat * 4);
+  pl.nblk = (pl.nslots + cog::kStatBlock - 1) / cog::kStatBlock;
+  pl.off_statout = off;
+  off += align256((size_t)kChunk * pl.nblk * cog::kStat * 4);
   pl.total = off;
   return pl;
 }
@@ -203,23 +205,6 @@ cog_status ensure_stage(cog_ctx *h, size_t in_bytes, size_t mask_bytes) {
   return COG_OK;
 }
 
-void fill_infos(cog_ctx *h, int64_t first_frame, int n, cog_step_info *infos) {
-  const int ns = h->plan.nslots;
-  for (int f = 0; f < n; ++f) {
-    int64_t s[cog::kStat] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const uint32_t *row = h->host_partials.data() + (size_t)f * ns * cog::kStat;
-    for (int i = 0; i < ns; ++i)
-      for (int k = 0; k < cog::kStat; ++k) s[k] += row[(size_t)i * cog::kStat + k];
-    cog_step_info &o = infos[f];
-    o.frame = first_frame + f;
-    for (int k = 0; k < 4; ++k) o.n_stage[k] = s[k];
-    o.n3_bg = s[4];
-    o.n_fg = s[5];
-    o.illum_flag = ((double)s[3] > (double)h->p.illum_frac * (double)h->plan.P) ? 1 : 0;
-    o.reserved = 0;
-  }
-}
-
 // Runs n frames starting at frames (device) writing masks (device or NULL).
 cog_status run_frames(cog_ctx *h, const void *dframes, int n, uint8_t *dmasks, bool want_stats,
                       cog_step_info *infos) {
@@ -245,13 +230,20 @@ cog_status run_frames(cog_ctx *h, const void *dframes, int n, uint8_t *dmasks, b
       e = cog::launch_gmm(pl.C, pl.K, h->p.dtype == COG_F32, h->buf, fr, h->kp, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "kernel launch");
     if (want_stats) {
-      const size_t nb = (size_t)cnt * pl.nslots * cog::kStat * 4;
-      h->host_partials.resize((size_t)cnt * pl.nslots * cog::kStat);
-      e = hipMemcpyAsync(h->host_partials.data(), fr.partials, nb, hipMemcpyDeviceToHost,
-                         h->stream);
+      // per-frame sums on the device, then a small copy
+      cog::StatJob job{};
+      job.partials = fr.partials;
+      job.out = reinterpret_cast<uint32_t *>(h->dstate + pl.off_statout);
+      job.nslots = pl.nslots;
+      job.nframes = cnt;
+      e = cog::launch_stats(job, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "statistics launch");
+      const size_t nw = (size_t)cnt * pl.nblk * cog::kStat;
+      h->host_stats.resize(nw);
+      e = hipMemcpyAsync(h->host_stats.data(), job.out, nw * 4, hipMemcpyDeviceToHost, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "statistics copy");
-      fill_infos(h, h->frame + done, cnt, infos + done);
+      cog_rt::fill_infos(h, h->frame + done, cnt, h->host_stats.data(), infos + done);
     }
     done += cnt;
   }

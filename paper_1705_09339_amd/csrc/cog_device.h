@@ -52,6 +52,38 @@ struct Frames {
   int nframes;
 };
 
+// ---- batched tick ------------------------------------------------------------
+// One stream's work in a tick: its frames, state and parameters.  The tick's
+// 64-pixel tiles are numbered consecutively over its items in item order;
+// item i owns tiles [tile_begin, tile_begin + ceil(P / 64)).
+struct TickItem {
+  Frames fr;
+  Buffers b;
+  KParams kp;
+  int32_t pad;
+  int64_t tile_begin;
+};
+
+// Head of one class's work list.  queue is the dynamic schedule's next unit
+// and must be zero when the launch starts (the host uploads it as zero).
+struct TickHead {
+  int64_t total_tiles;
+  int32_t n_items;
+  int32_t group;     // tiles per schedule unit
+  uint32_t queue;
+  uint32_t pad[11];
+};
+
+// Per-frame reduction of the per-tile counters of one run of frames:
+// out[f][blk][kStat] = sums over the slots of block blk (kStatBlock slots).
+struct StatJob {
+  const uint32_t *partials;  // [nframes][nslots][kStat]
+  uint32_t *out;             // [nframes][ceil(nslots / kStatBlock)][kStat]
+  int32_t nslots;
+  int32_t nframes;
+};
+constexpr int kStatBlock = 4096;
+
 // Launchers (cog_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_train(int C, int K, bool f32in, bool prior, bool aos, const Buffers &b,
                         const void *frames, int64_t stride, int n, const KParams &kp,
@@ -60,5 +92,18 @@ hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, 
                           const KParams &kp, hipStream_t s);
 hipError_t launch_gmm(int C, int K, bool f32in, const Buffers &b, const Frames &fr,
                       const KParams &kp, hipStream_t s);
+// Persistent tick over one class (C, K, input type) of streams: grid
+// workgroups of one wave; dynamic = 0 deals units round-robin by workgroup,
+// 1 hands them out from head->queue.
+hipError_t launch_tick(int C, int K, bool f32in, bool lp, TickHead *head, const TickItem *items,
+                       int grid, int dynamic, hipStream_t s);
+// Statistics reduction: one job by value, or n jobs from a device table
+// (grid covers max_blocks x max_frames x n).
+hipError_t launch_stats(const StatJob &job, hipStream_t s);
+hipError_t launch_stats_table(const StatJob *jobs, int n, int max_blocks, int max_frames,
+                              hipStream_t s);
+// Workgroups of the class's tick kernel one compute unit keeps resident
+// (0 if the query fails).
+int tick_blocks_per_cu(int C, int K, bool f32in, bool lp);
 
 }  // namespace cog

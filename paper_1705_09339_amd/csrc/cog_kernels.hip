@@ -407,6 +407,7 @@ struct InStage {
   }
 };
 
+
 // Compiler-level ordering of LDS accesses between the lanes of one wave (the
 // hardware executes a wave's LDS instructions in order).
 __device__ __forceinline__ void wave_sync() {
@@ -1190,18 +1191,30 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
 //  - the mask and statistics stores are bounds-checked buffer stores;
 //  - for u8 input up to K = 5 the register budget keeps five waves per SIMD (a 640x480
 //    frame is 4.7 waves per SIMD: all of them stay resident).
+// LDS of one wave running cascade_tile: the tile's prior records (when
+// staged) and the input ring.
+template <int C, bool F32, bool LP>
+struct TileLds {
+  static constexpr int NB = 8;  // frames per input block
+  uint4 prior[LP ? 64 * prior_bytes(C) / 16 : 1];
+  uint32_t in[NB * InStage<C, F32, NB>::NDW * 64];
+};
+
+// The cascade over fr.nframes frames for the 64 pixels of one tile (tile =
+// index of the 64-pixel run within the stream), one pixel per lane.  Shared
+// by the one-stream kernel and the batched tick.
 template <int C, int K, bool F32, bool LP>
-__global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
+__device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr, const KParams &kp,
+                                             int64_t tile, int lane, TileLds<C, F32, LP> &lds) {
   constexpr int R = rec_floats(C, K);
   constexpr int RG = rga_floats(C);
   constexpr int PB = prior_bytes(C);
-  constexpr int NB = 8;  // frames per input block
+  constexpr int NB = TileLds<C, F32, LP>::NB;
   using Stage = InStage<C, F32, NB>;
-  __shared__ uint4 s_prior[LP ? 64 * PB / 16 : 1];
-  __shared__ uint32_t s_in[NB * Stage::NDW * 64];
+  uint4 *s_prior = lds.prior;
+  uint32_t *s_in = lds.in;
 
-  const int lane = threadIdx.x;
-  const int64_t tile0 = (int64_t)blockIdx.x * 64;
+  const int64_t tile0 = tile * 64;
   const int64_t p = tile0 + lane;
   const bool valid = p < b.P;
   const int64_t pcl = valid ? p : b.P - 1;
@@ -1240,7 +1253,7 @@ __global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buff
   // statistics word in a frame's row; out-of-range lanes are dropped by the
   // buffer stores' bounds check
   const int moff = valid ? (int)p : 0x7fffffff;
-  const int soff = lane < kStat ? (int)((int64_t)blockIdx.x * kStat + lane) * 4 : 0x7fffffff;
+  const int soff = lane < kStat ? (int)(tile * kStat + lane) * 4 : 0x7fffffff;
   const int srow = fr.nslots * kStat * 4;  // bytes per statistics row
 
   // misalignment of the tile's input run within 4 bytes, frame by frame
@@ -1344,8 +1357,9 @@ __global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buff
       }
 #pragma unroll
       for (int c = 0; c < C; ++c) xp[c] = x[c];
+      // masks are streamed out: non-temporal (cache policy bit 1)
       __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(lab ? 255 : 0), mr, moff,
-                                           k * (int)fr.mstride, 0);
+                                           k * (int)fr.mstride, 2);
       if (fr.partials) {
         const uint32_t c0 = (uint32_t)__popcll(__ballot(st == 0));
         const uint32_t c1 = (uint32_t)__popcll(__ballot(st == 1));
@@ -1375,6 +1389,127 @@ __global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buff
   if (lane == 0) b.labels[tile0 >> 6] = bal;
 }
 
+template <int C, int K, bool F32, bool LP>
+__global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
+  __shared__ TileLds<C, F32, LP> lds;
+  // Tiles follow the workgroup order, which the dispatcher deals round-robin
+  // over the XCDs: the spatially clustered survivor work (foreground, bimodal
+  // regions) is spread evenly over the chip.  (Contiguous tile runs per XCD
+  // share boundary cache lines but concentrate that work; measured slower.)
+  cascade_tile<C, K, F32, LP>(b, fr, kp, blockIdx.x, threadIdx.x, lds);
+}
+
+// ============================================================================
+// Batched tick: many streams of one class in one persistent launch.  The
+// tick's tiles (64 pixels each) are numbered over its items; a schedule unit
+// is `group` consecutive tiles.  Units go round-robin over the workgroups
+// (static) or are taken from an atomic counter (dynamic); either way a
+// wave's units increase, so its item cursor only moves forward.  Item and
+// slot descriptors are read through the constant address space, so they
+// arrive in scalar registers.
+typedef const __attribute__((address_space(4))) TickItem CTickItem;
+typedef const __attribute__((address_space(4))) TickHead CTickHead;
+
+// A descriptor field copied out through the constant address space, word by
+// word (the copy constructors do not take address-space-4 references).
+template <typename T>
+__device__ __forceinline__ T const_copy(const T *src) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor fields are whole words");
+  typedef const __attribute__((address_space(4))) uint32_t CWord;
+  CWord *w = (CWord *)src;
+  T v;
+  uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = w[i];
+  return v;
+}
+
+__device__ __forceinline__ int take_unit(uint32_t *queue, int lane) {
+  uint32_t v = 0u;
+  if (lane == 0) v = atomicAdd(queue, 1u);
+  return (int)__builtin_amdgcn_readfirstlane(v);
+}
+
+// Tile and unit indices are 32-bit: the host keeps a tick below 2^31 tiles.
+template <int C, int K, bool F32, bool LP>
+__global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_tick(TickHead *head,
+                                                                      const TickItem *items,
+                                                                      int dynamic) {
+  __shared__ TileLds<C, F32, LP> lds;
+  const int lane = threadIdx.x;
+  CTickHead *ch = (CTickHead *)head;
+  CTickItem *ci = (CTickItem *)items;
+  const int total = (int)ch->total_tiles;
+  const int group = ch->group;
+  const int units = (total + group - 1) / group;
+  uint32_t *queue = &head->queue;
+  int u = dynamic ? take_unit(queue, lane) : (int)blockIdx.x;
+  int it = 0;
+  while (u < units) {
+    // the next unit is requested before this one runs
+    const int nxt = dynamic ? take_unit(queue, lane) : u + (int)gridDim.x;
+    const int t1 = u < units - 1 ? (u + 1) * group : total;
+    for (int t = u * group; t < t1; ++t) {
+      while (it + 1 < ch->n_items && (int)ci[it + 1].tile_begin <= t) ++it;
+      const Frames fr = const_copy(&items[it].fr);
+      const Buffers b = const_copy(&items[it].b);
+      const KParams kp = const_copy(&items[it].kp);
+      cascade_tile<C, K, F32, LP>(b, fr, kp, t - (int)ci[it].tile_begin, lane, lds);
+    }
+    u = nxt;
+  }
+}
+
+// Statistics reduction: workgroup (blk, f) sums counters of slots
+// [blk * kStatBlock, ...) of frame f.
+__device__ __forceinline__ void stats_block(const StatJob &j, int blk, int f) {
+  __shared__ uint32_t red[kNW][kStat];
+  const int tid = threadIdx.x;
+  const int64_t s0 = (int64_t)blk * kStatBlock;
+  const int64_t s1 = s0 + kStatBlock < j.nslots ? s0 + kStatBlock : j.nslots;
+  uint32_t acc[kStat];
+#pragma unroll
+  for (int k = 0; k < kStat; ++k) acc[k] = 0u;
+  const uint4 *row = reinterpret_cast<const uint4 *>(j.partials + (int64_t)f * j.nslots * kStat);
+  for (int64_t i = s0 + tid; i < s1; i += kNT) {
+    const uint4 a = row[2 * i], c = row[2 * i + 1];
+    acc[0] += a.x; acc[1] += a.y; acc[2] += a.z; acc[3] += a.w;
+    acc[4] += c.x; acc[5] += c.y; acc[6] += c.z; acc[7] += c.w;
+  }
+#pragma unroll
+  for (int k = 0; k < kStat; ++k) {
+    uint32_t v = acc[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    acc[k] = v;
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < kStat; ++k) red[tid >> 6][k] = acc[k];
+  }
+  __syncthreads();
+  if (tid < kStat) {
+    uint32_t v = 0u;
+#pragma unroll
+    for (int w = 0; w < kNW; ++w) v += red[w][tid];
+    const int nblk = (j.nslots + kStatBlock - 1) / kStatBlock;
+    j.out[((int64_t)f * nblk + blk) * kStat + tid] = v;
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_stats(StatJob j) {
+  if ((int)blockIdx.y >= j.nframes) return;
+  if ((int64_t)blockIdx.x * kStatBlock >= j.nslots) return;
+  stats_block(j, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kNT) void k_stats_table(const StatJob *jobs) {
+  const StatJob j = jobs[blockIdx.z];
+  if ((int)blockIdx.y >= j.nframes) return;
+  if ((int64_t)blockIdx.x * kStatBlock >= j.nslots) return;
+  stats_block(j, blockIdx.x, blockIdx.y);
+}
+
 // ============================================================================
 // Plain Stauffer-Grimson baseline: every pixel runs the mixture step every
 // frame (alpha fixed), one wave per 64 pixels and one pixel per lane, the
@@ -1383,7 +1518,8 @@ __global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buff
 template <int C, int K, bool F32>
 __global__ __launch_bounds__(64) void k_gmm(Buffers b, Frames fr, KParams kp) {
   const int lane = threadIdx.x;
-  const int64_t tile0 = (int64_t)blockIdx.x * 64;
+  const int64_t tile = blockIdx.x;
+  const int64_t tile0 = tile * 64;
   const int64_t p = tile0 + lane;
   const bool valid = p < b.P;
   const int64_t rem = b.P - tile0;
@@ -1412,14 +1548,15 @@ __global__ __launch_bounds__(64) void k_gmm(Buffers b, Frames fr, KParams kp) {
         int l, mp;
         mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
         lab = l != 0;
-        if (fr.mask) fr.mask[(int64_t)f * fr.mstride + p] = lab ? 255 : 0;
+        if (fr.mask)
+          __builtin_nontemporal_store((uint8_t)(lab ? 255 : 0), fr.mask + (int64_t)f * fr.mstride + p);
       }
       if (fr.partials) {
         const uint32_t nv = (uint32_t)__popcll(__ballot(valid));
         const uint32_t nf = (uint32_t)__popcll(__ballot(valid && lab));
         if (lane < kStat) {
           const uint32_t v = lane == 3 ? nv : lane == 4 ? nv - nf : lane == 5 ? nf : 0u;
-          fr.partials[((int64_t)f * fr.nslots + blockIdx.x) * kStat + lane] = v;
+          fr.partials[((int64_t)f * fr.nslots + tile) * kStat + lane] = v;
         }
       }
     }
@@ -1501,6 +1638,55 @@ hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, 
 #undef COG_CASCW
 #undef COG_CASCD
 #undef COG_CASC
+  return hipGetLastError();
+}
+
+hipError_t launch_tick(int C, int K, bool f32in, bool lp, TickHead *head, const TickItem *items,
+                       int grid, int dynamic, hipStream_t s) {
+  if (grid <= 0) return hipErrorInvalidValue;
+#define COG_TICK(KK, CC, FF, LL) \
+  hipLaunchKernelGGL((k_tick<CC, KK, FF, LL>), dim3(grid), dim3(64), 0, s, head, items, dynamic)
+#define COG_TICK_LP(CC, FF) \
+  if (lp) { COG_K_CASES(COG_TICK, CC, FF, true) } else { COG_K_CASES(COG_TICK, CC, FF, false) }
+  if (C == 3 && !f32in) { COG_TICK_LP(3, false) }
+  else if (C == 3 && f32in) { COG_TICK_LP(3, true) }
+  else if (C == 1 && !f32in) { COG_TICK_LP(1, false) }
+  else if (C == 1 && f32in) { COG_TICK_LP(1, true) }
+  else return hipErrorInvalidValue;
+#undef COG_TICK_LP
+#undef COG_TICK
+  return hipGetLastError();
+}
+
+int tick_blocks_per_cu(int C, int K, bool f32in, bool lp) {
+  if (K < 1 || K > 8) return 0;
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define COG_OCC(KK, CC, FF, LL) \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tick<CC, KK, FF, LL>, 64, 0)
+#define COG_OCC_LP(CC, FF) \
+  if (lp) { COG_K_CASES(COG_OCC, CC, FF, true) } else { COG_K_CASES(COG_OCC, CC, FF, false) }
+  if (C == 3 && !f32in) { COG_OCC_LP(3, false) }
+  else if (C == 3 && f32in) { COG_OCC_LP(3, true) }
+  else if (C == 1 && !f32in) { COG_OCC_LP(1, false) }
+  else if (C == 1 && f32in) { COG_OCC_LP(1, true) }
+#undef COG_OCC_LP
+#undef COG_OCC
+  return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_stats(const StatJob &job, hipStream_t s) {
+  if (job.nframes <= 0 || job.nslots <= 0) return hipSuccess;
+  const unsigned nblk = (unsigned)((job.nslots + kStatBlock - 1) / kStatBlock);
+  hipLaunchKernelGGL(k_stats, dim3(nblk, (unsigned)job.nframes, 1), dim3(kNT), 0, s, job);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_table(const StatJob *jobs, int n, int max_blocks, int max_frames,
+                              hipStream_t s) {
+  if (n <= 0 || max_blocks <= 0 || max_frames <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stats_table, dim3((unsigned)max_blocks, (unsigned)max_frames, (unsigned)n),
+                     dim3(kNT), 0, s, jobs);
   return hipGetLastError();
 }
 

@@ -14,4 +14,5 @@ from .video import (  # noqa: F401
     random_stream,
     alternating_stream,
     step_stream,
+    latent_stream,
 )

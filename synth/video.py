@@ -288,3 +288,37 @@ def step_stream(n: int, h: int, w: int, c: int, v0, v1, t_step: int) -> np.ndarr
     out[:t_step] = np.asarray(v0, dtype=np.uint8)
     out[t_step:] = np.asarray(v1, dtype=np.uint8)
     return out
+
+
+# ---- latent-map streams ----------------------------------------------------------
+
+def latent_stream(n: int, channels: int = 64, h: int = 30, w: int = 40, seed: int = BASE_SEED + 4,
+                  noise: float = 0.1, drift_amp: float = 0.5, blob: bool = True,
+                  start: int = 0) -> np.ndarray:
+    """Frames [start, start + n) of a stream of f32 latent maps, flattened so
+    that every (channel, y, x) element is one single-channel pixel:
+    array [n, channels * h * w], element index (ch * h + y) * w + x.
+
+    Each channel is a fixed Gaussian spatial pattern plus a slow sinusoidal
+    drift of its own (period 300..900 frames, amplitude drift_amp) plus
+    per-frame N(0, noise^2) noise; with blob, a 6x6 patch moving along a
+    diagonal adds +2 to a quarter of the channels (a foreground object in
+    latent space).  Values stay roughly within [-5, 5].
+    """
+    lay = _rng(seed, _LAYOUT_KEY)
+    base = lay.normal(0.0, 1.0, size=(channels, h, w)).astype(np.float32)
+    period = lay.uniform(300.0, 900.0, size=channels)
+    phase = lay.uniform(0.0, 2.0 * math.pi, size=channels)
+    fg_ch = lay.permutation(channels)[: max(1, channels // 4)]
+    out = np.empty((n, channels * h * w), dtype=np.float32)
+    for i in range(n):
+        t = start + i
+        d = (drift_amp * np.sin(2.0 * math.pi * t / period + phase)).astype(np.float32)
+        fr = base + d[:, None, None]
+        fr = fr + _rng(seed, t).normal(0.0, noise, size=(channels, h, w)).astype(np.float32)
+        if blob:
+            y0 = (t // 2) % max(1, h - 6)
+            x0 = t % max(1, w - 6)
+            fr[fg_ch, y0:y0 + 6, x0:x0 + 6] += np.float32(2.0)
+        out[i] = fr.reshape(-1)
+    return out

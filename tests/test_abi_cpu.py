@@ -51,6 +51,10 @@ def test_struct_layouts_match_header(C, tmp_path):
         lines.append(f'printf("%zu\\n", offsetof(cog_params, {cfields[f]}));')
     for f, _ in C.cog_step_info._fields_:
         lines.append(f'printf("%zu\\n", offsetof(cog_step_info, {f}));')
+    for st in (C.cog_tick_item, C.cog_schedule):
+        lines.append(f'printf("%zu\\n", sizeof({st.__name__}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({st.__name__}, {f}));')
     lines.append("return 0;}")
     (tmp_path / "probe.c").write_text("\n".join(lines))
     exe = tmp_path / "probe"
@@ -62,6 +66,8 @@ def test_struct_layouts_match_header(C, tmp_path):
     offs = vals[2:]
     exp = [getattr(C.cog_params, f).offset for f in fields_p] + \
           [getattr(C.cog_step_info, f).offset for f, _ in C.cog_step_info._fields_]
+    for st in (C.cog_tick_item, C.cog_schedule):
+        exp += [ct.sizeof(st)] + [getattr(st, f).offset for f, _ in st._fields_]
     assert offs == exp
 
 
@@ -133,3 +139,24 @@ def test_null_context_calls_are_invalid(C):
     assert C.lib.cog_step(None, None, 0, None, 0, None) == C.COG_E_INVALID
     assert C.lib.cog_train_prior(None, None, 10, 0) == C.COG_E_INVALID
     C.lib.cog_destroy(None)
+
+
+def test_batch_create_without_device_reports_device_error(C):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(C.CogError) as ei:
+        C.cog_batch_create(None, 8)
+    assert ei.value.status == C.COG_E_DEVICE
+
+
+def test_null_batch_calls_are_invalid(C):
+    s = C.cog_schedule(0, 0, 1, 1)
+    assert C.lib.cog_batch_tick(None, None, 0) == C.COG_E_INVALID
+    assert C.lib.cog_batch_set_schedule(None, 3, 5, 0, ct.byref(s)) == C.COG_E_INVALID
+    assert C.lib.cog_batch_get_schedule(None, 3, 5, 0, ct.byref(s)) == C.COG_E_INVALID
+    assert C.lib.cog_batch_autotune(None, None, 0, 1, None) == C.COG_E_INVALID
+    out = ct.c_void_p(0)
+    assert C.lib.cog_batch_create(None, 0, ct.byref(out)) == C.COG_E_INVALID
+    assert C.lib.cog_batch_create(None, 5000, ct.byref(out)) == C.COG_E_INVALID
+    C.lib.cog_batch_destroy(None)
