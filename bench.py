@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-stream batched tick")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched tick")
     return ap.parse_args()
 
 
@@ -118,6 +120,9 @@ def main():
     from paper_1705_09339_amd import cog as C
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.batch_only:
+        print(json.dumps({"batch": batch_leg(args, C)}), flush=True)
+        return
     spec = synth.preset(args.workload)
     P, T, N, K = spec.pixels, spec.frames, spec.n_train, spec.K
     F = T - N
@@ -270,10 +275,176 @@ def main():
         "roofline": roof,
     }
 
+    if not args.no_batch:
+        del dev, masks
+        torch.cuda.empty_cache()
+        res["batch"] = batch_leg(args, C)
+
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(frames, spec, args.cpu_seconds)
 
     print(json.dumps(res), flush=True)
+
+
+# ---- batched tick: 64 streams of mixed sizes --------------------------------------
+BATCH_WORKLOAD = "batch-64-mixed"
+BATCH_RING = 32    # distinct frames per stream, played forwards then backwards
+
+
+def batch_streams():
+    """16 RGB u8 streams each at 320x240, 640x480 and 1280x720 (K=5), and 16
+    latent-map streams (64 channels of 30x40 f32 as single-channel pixels,
+    K=3); lengths after training drawn in [300, 2000]."""
+    rng = np.random.default_rng(170509339 + 4)
+    out = []
+    for w, h in ((320, 240), (640, 480), (1280, 720)):
+        for i in range(16):
+            out.append(dict(kind="u8", w=w, h=h, c=3, K=5, seed=170509339 + 4 + 1000 * len(out),
+                            length=int(rng.integers(300, 2001))))
+    for i in range(16):
+        out.append(dict(kind="latent", w=30 * 40 * 64, h=1, c=1, K=3,
+                        seed=170509339 + 4 + 1000 * len(out), length=int(rng.integers(300, 2001))))
+    return out
+
+
+def batch_leg(args, C):
+    """The 64-stream batched workload: every stream trained on its first 100
+    frames, then ticked until the longest ends; a tick advances every
+    unfinished stream by F frames in one graph replay.  Timed with the
+    inputs resident in HBM (a ring of distinct frames per stream)."""
+    import torch
+
+    import synth
+    from synth.device import DeviceScene
+
+    N = 100
+    R2 = 2 * BATCH_RING
+    specs = batch_streams()
+    stream = torch.cuda.Stream()
+    t0 = time.time()
+    ctxs, rings, masks, trains = [], [], [], []
+    with torch.cuda.stream(stream):
+        for sp in specs:
+            if sp["kind"] == "u8":
+                sc = DeviceScene(sp["w"], sp["h"], sp["seed"])
+                tr = sc.frames(0, N).view(N, -1)
+                ring = sc.frames(N, BATCH_RING).view(BATCH_RING, -1)
+                p = C.cog_default_params(sp["w"], sp["h"], 3, C.COG_U8, sp["K"])
+            else:
+                lat = synth.latent_stream(N + BATCH_RING, seed=sp["seed"])
+                tr = torch.from_numpy(lat[:N]).cuda()
+                ring = torch.from_numpy(lat[N:]).cuda()
+                p = C.cog_default_params(sp["w"], 1, 1, C.COG_F32, sp["K"], in_lo=-5.0, in_hi=5.0)
+            rings.append(torch.cat([ring, ring.flip(0)]).contiguous())
+            trains.append(tr)
+            ctxs.append(C.CogStream(p, stream=stream))
+            masks.append(torch.empty((8, sp["w"] * sp["h"]), dtype=torch.uint8, device="cuda"))
+    stream.synchronize()
+    log(f"batch: {len(specs)} streams generated in {time.time() - t0:.1f} s")
+    P = np.array([sp["w"] * sp["h"] for sp in specs], dtype=np.int64)
+    L = np.array([sp["length"] for sp in specs], dtype=np.int64)
+    fbytes = np.array([r.shape[1] * r.element_size() for r in rings], dtype=np.int64)
+    ring_ptr = np.array([r.data_ptr() for r in rings], dtype=np.uint64)
+    work = int((P * L).sum())
+
+    def train_all():
+        for c, tr in zip(ctxs, trains):
+            c.reset()
+            c.train_prior(tr)
+        stream.synchronize()
+
+    def run_batched(b, F, lat=None):
+        table = C.TickTable(len(specs))
+        table.view["ctx"] = [c.h for c in ctxs]
+        table.view["masks"] = [m.data_ptr() for m in masks]
+        done = np.zeros(len(specs), dtype=np.int64)
+        n_ticks = int(-(-L.max() // F))
+        evs = []
+        stream.synchronize()
+        ts = time.perf_counter()
+        for k in range(n_ticks):
+            nf = np.minimum(F, L - done)
+            table.view["nframes"] = nf
+            table.view["frames"] = ring_ptr + ((done % R2) * fbytes).astype(np.uint64)
+            if lat is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                table.tick(b.b)
+                e1.record(stream)
+                evs.append((e0, e1))
+            else:
+                table.tick(b.b)
+            done += nf
+        stream.synchronize()
+        wall = time.perf_counter() - ts
+        if lat is not None:
+            lat.extend(e0.elapsed_time(e1) for e0, e1 in evs)
+        return wall, n_ticks
+
+    def run_per_stream(F):
+        done = np.zeros(len(specs), dtype=np.int64)
+        n_ticks = int(-(-L.max() // F))
+        stream.synchronize()
+        ts = time.perf_counter()
+        for k in range(n_ticks):
+            for i, c in enumerate(ctxs):
+                n = int(min(F, L[i] - done[i]))
+                if n <= 0:
+                    continue
+                o = int(done[i] % R2)
+                c.step_frames(rings[i][o:o + n], masks[i][:n])
+                done[i] += n
+        stream.synchronize()
+        return time.perf_counter() - ts
+
+    res = {"workload": BATCH_WORKLOAD,
+           "streams": "16x320x240 + 16x640x480 + 16x1280x720 RGB u8 K=5, "
+                      "16x latent 64ch 30x40 f32 (C=1, K=3); lengths 300-2000 after 100 training frames",
+           "pixel_frames": work}
+    with torch.cuda.stream(stream):
+        b = C.CogBatch(stream, max_items=len(specs))
+        # training (every stream, one launch each), timed once
+        train_all()
+        ts = time.perf_counter()
+        train_all()
+        res["train_ms_all_streams"] = round((time.perf_counter() - ts) * 1e3, 3)
+        # autotune on the first F=1 tick, state restored afterwards
+        table = C.TickTable(len(specs))
+        table.view["ctx"] = [c.h for c in ctxs]
+        table.view["masks"] = [m.data_ptr() for m in masks]
+        table.view["nframes"] = 1
+        table.view["frames"] = ring_ptr
+        best = table.autotune(b.b, reps=5)
+        res["schedule_u8_k5"] = b.get_schedule(3, 5, C.COG_U8)
+        res["schedule_latent"] = b.get_schedule(1, 3, C.COG_F32)
+        for F in (1, 8):
+            train_all()
+            run_batched(b, F)  # warm-up (graph capture)
+            train_all()
+            lat = []
+            wall, n_ticks = run_batched(b, F, lat)
+            res[f"f{F}"] = {"mpx_s": round(work / wall / 1e6, 1), "ticks": n_ticks,
+                            "ms_per_tick": round(wall / n_ticks * 1e3, 4),
+                            "gpu_tick_p50_ms": round(pct(lat, 50), 4),
+                            "gpu_tick_p99_ms": round(pct(lat, 99), 4)}
+            log(f"batch F={F}: {res[f'f{F}']}")
+        for cls in ((3, 5, C.COG_U8), (1, 3, C.COG_F32)):  # the defaults
+            b.set_schedule(*cls, blocks_per_cu=-1, dynamic=0, group=4, use_graph=1)
+        train_all()
+        run_batched(b, 1)
+        train_all()
+        wall, n_ticks = run_batched(b, 1)
+        res["f1_default_schedule_mpx_s"] = round(work / wall / 1e6, 1)
+        train_all()
+        wall = run_per_stream(1)
+        res["f1_per_stream_launches_mpx_s"] = round(work / wall / 1e6, 1)
+        log(f"batch: default schedule {res['f1_default_schedule_mpx_s']} Mpx/s, "
+            f"per-stream launches {res['f1_per_stream_launches_mpx_s']} Mpx/s")
+        b.close()
+        for c in ctxs:
+            c.close()
+    return res
 
 
 def cpu_baseline(frames, spec, budget_s):

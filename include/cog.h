@@ -226,7 +226,7 @@ cog_status cog_batch_autotune(cog_batch *b, const cog_tick_item *items, int32_t 
                               cog_schedule *best);
 
 /* Set or read the schedule of one class (channels, K, dtype).  Classes
- * without a set schedule use {0, 0, 1, 1}.  COG_E_INVALID for bad values. */
+ * without a set schedule use {-1, 0, 4, 1}.  COG_E_INVALID for bad values. */
 cog_status cog_batch_set_schedule(cog_batch *b, int32_t channels, int32_t K, int32_t dtype,
                                   const cog_schedule *s);
 cog_status cog_batch_get_schedule(cog_batch *b, int32_t channels, int32_t K, int32_t dtype,
@@ -234,6 +234,91 @@ cog_status cog_batch_get_schedule(cog_batch *b, int32_t channels, int32_t K, int
 
 /* Destroy a batch; NULL-safe.  Waits for its stream.  The contexts stay. */
 void cog_batch_destroy(cog_batch *b);
+
+/* ---- Serving loop -------------------------------------------------------------
+ * A request loop over many camera streams (the paper's real-time setting,
+ * §1 and §3.2): frames are submitted as they arrive; a scheduler thread
+ * gathers, whenever fewer than `depth` ticks are in flight, the oldest
+ * pending submission of every stream into one batched tick (continuous
+ * batching: frames that arrive while a tick runs join the next one), so the
+ * work of different requests overlaps on the device.  Every stream's state
+ * stays resident in device memory from open to close; a stream is admitted
+ * only if its state fits the HBM budget (state buffers of closed streams are
+ * pooled and reused).  Each stream's masks and state are bit-identical to
+ * the same frames run alone through cog_step_frames.
+ *
+ * Threading: every call may come from any thread; calls are serialised by
+ * the server.  Frames and masks are device buffers owned by the caller and
+ * must stay valid until the frame's completion is reported. */
+typedef struct cog_server cog_server;
+
+typedef struct {
+  int32_t stream_id;
+  int32_t nframes;      /* frames of the submission */
+  int64_t tag;          /* the caller's tag from cog_server_submit */
+  double t_submit_us;   /* host clock at submission, microseconds since cog_server_create */
+  double t_done_us;     /* host clock when the tick was seen complete */
+  int32_t status;       /* COG_OK, or the error that failed the tick */
+  int32_t reserved;
+} cog_completion;
+
+typedef struct {
+  int64_t ticks;            /* batched ticks issued */
+  int64_t frames;           /* frames completed */
+  int64_t pixel_frames;     /* pixels x frames completed */
+  int64_t streams_open;
+  int64_t streams_admitted; /* cog_server_open successes */
+  int64_t streams_rejected; /* cog_server_open refusals for lack of budget */
+  int64_t bytes_budget;     /* device bytes the server may hold for stream state */
+  int64_t bytes_allocated;  /* held: open streams' state plus the reuse pool */
+  int64_t bytes_in_use;     /* open streams' state */
+  int64_t pending;          /* submissions not yet issued */
+  int64_t in_flight;        /* ticks issued and not yet complete */
+} cog_server_stats;
+
+/* Create a server on hip_stream (NULL: the server creates its own stream)
+ * holding at most hbm_budget bytes of stream state and max_streams streams
+ * (1..4096); depth = ticks in flight (1..8).  Errors: COG_E_INVALID,
+ * COG_E_OOM, COG_E_DEVICE. */
+cog_status cog_server_create(void *hip_stream, size_t hbm_budget, int32_t max_streams,
+                             int32_t depth, cog_server **out);
+
+/* Admit a stream: reserve its state within the budget, create its context
+ * (parameters as for cog_create; cascade path, 64-pixel tiles) and run its
+ * training on n_train device frames.  *id receives the stream's id.
+ * COG_E_OOM when the state does not fit the budget or max_streams streams
+ * are open; other errors as for cog_create and cog_train_prior. */
+cog_status cog_server_open(cog_server *s, const cog_params *p, const void *train_frames,
+                           int32_t n_train, int32_t *id);
+
+/* Queue nframes consecutive device frames of stream id (masks: nframes x H x W
+ * device bytes, or NULL); returns at once.  COG_E_INVALID for an unknown or
+ * closing stream or bad counts (1..64 frames); COG_E_DEVICE if the server
+ * has failed. */
+cog_status cog_server_submit(cog_server *s, int32_t id, const void *frames, int32_t nframes,
+                             uint8_t *masks, int64_t tag);
+
+/* Close stream id: its queued frames still complete; then its state buffer
+ * returns to the pool.  COG_E_INVALID for an unknown id. */
+cog_status cog_server_close(cog_server *s, int32_t id);
+
+/* Move up to max completions (oldest first) to out; *n receives the count.
+ * Waits up to wait_us microseconds when none is ready. */
+cog_status cog_server_poll(cog_server *s, cog_completion *out, int32_t max, int32_t *n,
+                           int64_t wait_us);
+
+/* Wait until every submitted frame (of stream id, or of all streams if
+ * id < 0) has completed. */
+cog_status cog_server_drain(cog_server *s, int32_t id);
+
+/* Canonical state of stream id (see cog_export_state), after its submitted
+ * frames complete. */
+cog_status cog_server_export(cog_server *s, int32_t id, void *host_dst, size_t bytes);
+
+cog_status cog_server_stats_get(cog_server *s, cog_server_stats *out);
+
+/* Stop the scheduler, wait for the device, free everything; NULL-safe. */
+void cog_server_destroy(cog_server *s);
 
 #ifdef __cplusplus
 }

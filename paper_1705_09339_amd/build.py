@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcog.so")
 SOURCES = [os.path.join(CSRC, "cog_kernels.hip"), os.path.join(CSRC, "cog_api.cpp"),
-           os.path.join(CSRC, "cog_batch.cpp")]
+           os.path.join(CSRC, "cog_batch.cpp"), os.path.join(CSRC, "cog_server.cpp")]
 HEADERS = [os.path.join(CSRC, "cog_device.h"), os.path.join(CSRC, "cog_ctx.h"),
            os.path.join(ROOT, "include", "cog.h")]
 

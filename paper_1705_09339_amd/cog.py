@@ -71,6 +71,23 @@ class cog_schedule(ct.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class cog_completion(ct.Structure):
+    _fields_ = [
+        ("stream_id", ct.c_int32), ("nframes", ct.c_int32), ("tag", ct.c_int64),
+        ("t_submit_us", ct.c_double), ("t_done_us", ct.c_double), ("status", ct.c_int32),
+        ("reserved", ct.c_int32),
+    ]
+
+
+class cog_server_stats(ct.Structure):
+    _fields_ = [(f, ct.c_int64) for f in (
+        "ticks", "frames", "pixel_frames", "streams_open", "streams_admitted", "streams_rejected",
+        "bytes_budget", "bytes_allocated", "bytes_in_use", "pending", "in_flight")]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class CogError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -102,6 +119,15 @@ def _load(path: str = LIB_PATH):
         "cog_batch_set_schedule": ([V, ct.c_int32, ct.c_int32, ct.c_int32, P(cog_schedule)], ct.c_int),
         "cog_batch_get_schedule": ([V, ct.c_int32, ct.c_int32, ct.c_int32, P(cog_schedule)], ct.c_int),
         "cog_batch_destroy": ([V], None),
+        "cog_server_create": ([V, ct.c_size_t, ct.c_int32, ct.c_int32, P(V)], ct.c_int),
+        "cog_server_open": ([V, P(cog_params), V, ct.c_int32, P(ct.c_int32)], ct.c_int),
+        "cog_server_submit": ([V, ct.c_int32, V, ct.c_int32, V, ct.c_int64], ct.c_int),
+        "cog_server_close": ([V, ct.c_int32], ct.c_int),
+        "cog_server_poll": ([V, P(cog_completion), ct.c_int32, P(ct.c_int32), ct.c_int64], ct.c_int),
+        "cog_server_drain": ([V, ct.c_int32], ct.c_int),
+        "cog_server_export": ([V, ct.c_int32, V, ct.c_size_t], ct.c_int),
+        "cog_server_stats_get": ([V, P(cog_server_stats)], ct.c_int),
+        "cog_server_destroy": ([V], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -116,7 +142,10 @@ EXPORTED = ("cog_default_params", "cog_state_bytes", "cog_canonical_bytes", "cog
             "cog_train_prior", "cog_step", "cog_step_frames", "cog_reset", "cog_destroy",
             "cog_export_state", "cog_import_state", "cog_kde_weights", "cog_last_error",
             "cog_batch_create", "cog_batch_tick", "cog_batch_autotune", "cog_batch_set_schedule",
-            "cog_batch_get_schedule", "cog_batch_destroy")
+            "cog_batch_get_schedule", "cog_batch_destroy",
+            "cog_server_create", "cog_server_open", "cog_server_submit", "cog_server_close",
+            "cog_server_poll", "cog_server_drain", "cog_server_export", "cog_server_stats_get",
+            "cog_server_destroy")
 
 
 def _check(rc: int, h=None):
@@ -341,8 +370,8 @@ def cog_batch_autotune(b: int, entries, reps: int = 3) -> dict:
 
 
 def cog_batch_set_schedule(b: int, channels: int, K: int, dtype: int, **kw) -> None:
-    s = cog_schedule(blocks_per_cu=kw.get("blocks_per_cu", 0), dynamic=kw.get("dynamic", 0),
-                     group=kw.get("group", 1), use_graph=kw.get("use_graph", 1))
+    s = cog_schedule(blocks_per_cu=kw.get("blocks_per_cu", -1), dynamic=kw.get("dynamic", 0),
+                     group=kw.get("group", 4), use_graph=kw.get("use_graph", 1))
     _check(lib.cog_batch_set_schedule(b, channels, K, dtype, ct.byref(s)))
 
 
@@ -378,6 +407,105 @@ class CogBatch:
         if self.b:
             cog_batch_destroy(self.b)
             self.b = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class TickTable:
+    """A reusable cog_tick_item array for tight tick loops: the fields are
+    exposed as numpy columns (ctx, frames, masks, nframes), so a caller
+    updates pointers and counts without building Python objects per tick."""
+
+    _dtype = np.dtype([("ctx", np.uint64), ("frames", np.uint64), ("masks", np.uint64),
+                       ("nframes", np.int32), ("reserved", np.int32), ("infos", np.uint64)])
+
+    def __init__(self, n: int):
+        assert self._dtype.itemsize == ct.sizeof(cog_tick_item)
+        self.n = n
+        self._arr = (cog_tick_item * max(n, 1))()
+        self.view = np.frombuffer(self._arr, dtype=self._dtype, count=n)
+
+    def tick(self, b: int, n: Optional[int] = None) -> None:
+        _check(lib.cog_batch_tick(b, self._arr, self.n if n is None else n))
+
+    def autotune(self, b: int, reps: int = 3) -> dict:
+        best = cog_schedule()
+        _check(lib.cog_batch_autotune(b, self._arr, self.n, reps, ct.byref(best)))
+        return best.as_dict()
+
+
+# ---- serving loop ------------------------------------------------------------------
+
+class CogServer:
+    """A serving loop (cog_server_*): streams are opened within an HBM budget,
+    frames submitted as they arrive, completions polled."""
+
+    def __init__(self, hbm_budget: int, max_streams: int = 256, depth: int = 2, stream=None):
+        s = ct.c_void_p(0)
+        _check(lib.cog_server_create(_stream_ptr(stream), int(hbm_budget), max_streams, depth,
+                                     ct.byref(s)))
+        self.s = s.value
+        self.params = {}
+
+    def open(self, params: cog_params, train_frames) -> int:
+        fp, fdev, keep = _ptr(train_frames)
+        if not fdev:
+            raise ValueError("training frames must be device memory")
+        sid = ct.c_int32(-1)
+        _check(lib.cog_server_open(self.s, ct.byref(params), fp, len(train_frames), ct.byref(sid)))
+        del keep
+        self.params[sid.value] = params
+        return sid.value
+
+    def submit(self, sid: int, frames, masks=None, tag: int = 0, nframes: Optional[int] = None):
+        fp, fdev, _ = _ptr(frames)
+        mp, mdev, _ = _ptr(masks)
+        if not fdev or (masks is not None and not mdev):
+            raise ValueError("frames and masks must be device memory")
+        n = 1 if nframes is None else nframes
+        _check(lib.cog_server_submit(self.s, sid, fp, n, mp, tag))
+
+    def submit_ptr(self, sid: int, frames_ptr: int, masks_ptr: int, tag: int, nframes: int = 1):
+        _check(lib.cog_server_submit(self.s, sid, frames_ptr, nframes, masks_ptr, tag))
+
+    def close_stream(self, sid: int):
+        _check(lib.cog_server_close(self.s, sid))
+
+    def poll(self, max_n: int = 1024, wait_us: int = 0):
+        buf = (cog_completion * max_n)()
+        n = ct.c_int32(0)
+        _check(lib.cog_server_poll(self.s, buf, max_n, ct.byref(n), wait_us))
+        return [dict(stream_id=c.stream_id, nframes=c.nframes, tag=c.tag, t_submit_us=c.t_submit_us,
+                     t_done_us=c.t_done_us, status=c.status) for c in buf[:n.value]]
+
+    def drain(self, sid: int = -1):
+        _check(lib.cog_server_drain(self.s, sid))
+
+    def export_state(self, sid: int) -> bytes:
+        nb = cog_canonical_bytes(self.params[sid])
+        buf = np.zeros(nb, dtype=np.uint8)
+        _check(lib.cog_server_export(self.s, sid, buf.ctypes.data, nb))
+        return buf.tobytes()
+
+    def stats(self) -> dict:
+        st = cog_server_stats()
+        _check(lib.cog_server_stats_get(self.s, ct.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.s:
+            lib.cog_server_destroy(self.s)
+            self.s = 0
 
     def __del__(self):
         try:

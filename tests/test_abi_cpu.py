@@ -51,7 +51,7 @@ def test_struct_layouts_match_header(C, tmp_path):
         lines.append(f'printf("%zu\\n", offsetof(cog_params, {cfields[f]}));')
     for f, _ in C.cog_step_info._fields_:
         lines.append(f'printf("%zu\\n", offsetof(cog_step_info, {f}));')
-    for st in (C.cog_tick_item, C.cog_schedule):
+    for st in (C.cog_tick_item, C.cog_schedule, C.cog_completion, C.cog_server_stats):
         lines.append(f'printf("%zu\\n", sizeof({st.__name__}));')
         for f, _ in st._fields_:
             lines.append(f'printf("%zu\\n", offsetof({st.__name__}, {f}));')
@@ -66,7 +66,7 @@ def test_struct_layouts_match_header(C, tmp_path):
     offs = vals[2:]
     exp = [getattr(C.cog_params, f).offset for f in fields_p] + \
           [getattr(C.cog_step_info, f).offset for f, _ in C.cog_step_info._fields_]
-    for st in (C.cog_tick_item, C.cog_schedule):
+    for st in (C.cog_tick_item, C.cog_schedule, C.cog_completion, C.cog_server_stats):
         exp += [ct.sizeof(st)] + [getattr(st, f).offset for f, _ in st._fields_]
     assert offs == exp
 
@@ -160,3 +160,25 @@ def test_null_batch_calls_are_invalid(C):
     assert C.lib.cog_batch_create(None, 0, ct.byref(out)) == C.COG_E_INVALID
     assert C.lib.cog_batch_create(None, 5000, ct.byref(out)) == C.COG_E_INVALID
     C.lib.cog_batch_destroy(None)
+
+
+def test_server_create_without_device_reports_device_error(C):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(C.CogError) as ei:
+        C.CogServer(1 << 30)
+    assert ei.value.status == C.COG_E_DEVICE
+
+
+def test_null_server_calls_are_invalid(C):
+    n = ct.c_int32(0)
+    assert C.lib.cog_server_submit(None, 0, None, 1, None, 0) == C.COG_E_INVALID
+    assert C.lib.cog_server_close(None, 0) == C.COG_E_INVALID
+    assert C.lib.cog_server_poll(None, None, 0, ct.byref(n), 0) == C.COG_E_INVALID
+    assert C.lib.cog_server_drain(None, -1) == C.COG_E_INVALID
+    out = ct.c_void_p(0)
+    assert C.lib.cog_server_create(None, 1 << 30, 0, 2, ct.byref(out)) == C.COG_E_INVALID
+    assert C.lib.cog_server_create(None, 1 << 30, 8, 9, ct.byref(out)) == C.COG_E_INVALID
+    assert C.lib.cog_server_create(None, 0, 8, 2, ct.byref(out)) == C.COG_E_INVALID
+    C.lib.cog_server_destroy(None)

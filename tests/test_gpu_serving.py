@@ -1,0 +1,232 @@
+"""Serving loop (cog_server_*): continuous batching of many streams.
+
+Frames of several streams arrive at seeded Poisson times from a submitting
+thread while the scheduler batches whatever is queued; streams open while
+others run.  Every stream's masks and final state must equal, bit for bit,
+the same frames run alone through cog_step_frames; every submission must
+complete exactly once, in order within its stream.  Admission by the HBM
+budget, reuse of closed streams' buffers and the error paths are checked
+too.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import gpu_params, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_09339_amd import cog
+    return cog
+
+
+def _synth(w, h, frames, seed_off):
+    spec = synth.preset("surveil-160x120-k3").with_(width=w, height=h, frames=frames, n_train=20,
+                                                    seed=synth.video.BASE_SEED + 700 + seed_off)
+    return synth.make_stream(spec)
+
+
+def stream_set(C):
+    """(name, params, frames [T, ...]); the first 20 frames train."""
+    lat = synth.latent_stream(70, channels=4, h=8, w=6, seed=synth.video.BASE_SEED + 790)
+    return [
+        ("u8c3k5-48x32", gpu_params(C, 48, 32, c=3, K=5), _synth(48, 32, 70, 1)),
+        ("u8c3k3-40x24", gpu_params(C, 40, 24, c=3, K=3), _synth(40, 24, 60, 2)),
+        ("u8c3k5-21x13", gpu_params(C, 21, 13, c=3, K=5), _synth(21, 13, 66, 3)),
+        ("u8c1k2-30x20", gpu_params(C, 30, 20, c=1, K=2),
+         np.ascontiguousarray(_synth(30, 20, 55, 4)[..., :1])),
+        ("f32c1k3-latent", gpu_params(C, 192, 1, c=1, K=3, dtype=1, in_lo=-5.0, in_hi=5.0),
+         lat.reshape(70, 192, 1)),
+    ]
+
+
+def alone(C, p, dev, n_train):
+    import torch
+    T = dev.shape[0] - n_train
+    masks = torch.zeros((T, p.width * p.height), dtype=torch.uint8, device="cuda")
+    s = C.CogStream(p, stream=torch.cuda.current_stream())
+    s.train_prior(dev[:n_train])
+    s.step_frames(dev[n_train:], masks)
+    torch.cuda.synchronize()
+    st = s.export_state()
+    s.close()
+    return masks.cpu().numpy(), st
+
+
+def test_serving_mix_equals_alone(C):
+    import torch
+    streams = stream_set(C)
+    devs = [torch.from_numpy(np.ascontiguousarray(fr)).cuda() for _, _, fr in streams]
+    torch.cuda.synchronize()
+    ref = [alone(C, p, d, 20) for (_, p, _), d in zip(streams, devs)]
+    masks = [torch.zeros((d.shape[0] - 20, p.width * p.height), dtype=torch.uint8, device="cuda")
+             for (_, p, _), d in zip(streams, devs)]
+    torch.cuda.synchronize()
+    srv = C.CogServer(hbm_budget=1 << 30, max_streams=8, depth=2)
+    rng = np.random.default_rng(7)
+    # submissions: (arrival time s, stream, first frame, n frames); streams 3
+    # and 4 open only after the others have run for a while
+    subs = []
+    for i, (_, p, fr) in enumerate(streams):
+        t = 0.0 if i < 3 else 0.004
+        f = 0
+        T = len(fr) - 20
+        while f < T:
+            n = int(min(T - f, rng.choice([1, 1, 1, 2, 3])))
+            t += float(rng.exponential(0.0001))
+            subs.append((t, i, f, n))
+            f += n
+    subs.sort()
+    ids = {}
+    tags = {}
+    say("serving: %d submissions over %d streams" % (len(subs), len(streams)))
+    t_start = time.perf_counter()
+    for t, i, f, n in subs:
+        while time.perf_counter() - t_start < t:
+            pass
+        if i not in ids:
+            ids[i] = srv.open(streams[i][1], devs[i][:20])
+        tag = len(tags)
+        tags[tag] = (i, f, n)
+        srv.submit(ids[i], devs[i][20 + f:20 + f + n], masks[i][f:f + n], tag=tag, nframes=n)
+    srv.drain()
+    comps = srv.poll(max_n=len(subs) + 10)
+    assert len(comps) == len(subs)
+    assert all(c["status"] == 0 for c in comps)
+    assert sorted(c["tag"] for c in comps) == list(range(len(subs)))
+    for i in range(len(streams)):
+        mine = [c["tag"] for c in comps if c["stream_id"] == ids[i]]
+        assert mine == sorted(mine), "completions out of order within a stream"
+        assert all(c["t_done_us"] >= c["t_submit_us"] for c in comps)
+    st = srv.stats()
+    say("serving stats", st)
+    assert st["frames"] == sum(len(fr) - 20 for _, _, fr in streams)
+    assert st["ticks"] < len(subs), "no batching happened"
+    states = {i: srv.export_state(ids[i]) for i in ids}
+    for i in ids:
+        srv.close_stream(ids[i])
+    srv.close()
+    for i, (name, p, fr) in enumerate(streams):
+        mg = masks[i].cpu().numpy()
+        assert np.array_equal(mg, ref[i][0]), (name, int((mg != ref[i][0]).sum()))
+        assert states[i] == ref[i][1], (name, "state differs")
+
+
+def test_admission_by_budget_and_pool_reuse(C):
+    import torch
+    fr = torch.from_numpy(_synth(32, 32, 24, 5)).cuda()
+    small_fr = fr[:20, :8, :8].contiguous()
+    torch.cuda.synchronize()  # the server reads them on its own stream
+    p = gpu_params(C, 32, 32, c=3, K=5)
+    nb = C.cog_state_bytes(p)
+    srv = C.CogServer(hbm_budget=int(nb * 2.5), max_streams=3, depth=2)
+    a = srv.open(p, fr[:20])
+    b = srv.open(p, fr[:20])
+    with pytest.raises(C.CogError) as e:
+        srv.open(p, fr[:20])
+    assert e.value.status == C.COG_E_OOM
+    st = srv.stats()
+    assert st["streams_open"] == 2 and st["streams_rejected"] == 1
+    assert st["bytes_in_use"] == 2 * nb and st["bytes_allocated"] == 2 * nb
+    srv.close_stream(a)
+    c = srv.open(p, fr[:20])  # reuses a's buffer
+    st = srv.stats()
+    assert st["bytes_allocated"] == 2 * nb and st["streams_open"] == 2
+    # a smaller stream fits beside them
+    small = gpu_params(C, 8, 8, c=3, K=3)
+    d = srv.open(small, small_fr)
+    with pytest.raises(C.CogError) as e:  # max_streams reached
+        srv.open(small, small_fr)
+    assert e.value.status == C.COG_E_OOM
+    for sid in (b, c, d):
+        srv.close_stream(sid)
+    assert srv.stats()["streams_open"] == 0
+    srv.close()
+
+
+def test_close_with_pending_frames_and_errors(C):
+    import torch
+    fr = torch.from_numpy(_synth(24, 16, 40, 6)).cuda()
+    masks = torch.zeros((20, 24 * 16), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()  # the server reads them on its own stream
+    p = gpu_params(C, 24, 16, c=3, K=3)
+    srv = C.CogServer(hbm_budget=1 << 28, max_streams=4)
+    sid = srv.open(p, fr[:20])
+    for k in range(20):
+        srv.submit(sid, fr[20 + k:21 + k], masks[k:k + 1], tag=k)
+    srv.close_stream(sid)  # queued frames still complete
+    srv.drain()
+    comps = srv.poll()
+    assert [c["tag"] for c in comps] == list(range(20))
+    assert srv.stats()["streams_open"] == 0
+    with pytest.raises(C.CogError) as e:
+        srv.submit(sid, fr[20:21], None, tag=99)
+    assert e.value.status == C.COG_E_INVALID
+    with pytest.raises(C.CogError):
+        srv.export_state(sid)
+    sid2 = srv.open(p, fr[:20])
+    for bad in (0, 65):
+        with pytest.raises(C.CogError) as e:
+            srv.submit(sid2, fr[20:21], None, tag=0, nframes=bad)
+        assert e.value.status == C.COG_E_INVALID
+    with pytest.raises(C.CogError) as e:
+        srv.open(gpu_params(C, 24, 16, c=3, K=3, path=1), fr[:20])
+    assert e.value.status == C.COG_E_UNSUPPORTED
+    with pytest.raises(C.CogError) as e:
+        srv.open(gpu_params(C, 24, 16, c=3, K=3, tile_px=128), fr[:20])
+    assert e.value.status == C.COG_E_UNSUPPORTED
+    # the stream after the failures still serves
+    srv.submit(sid2, fr[20:22], masks[:2], tag=5, nframes=2)
+    srv.drain(sid2)
+    assert [c["tag"] for c in srv.poll(wait_us=1000)] == [5]
+    srv.close()
+
+
+def test_concurrent_submitters_and_poller(C):
+    """Two submitting threads and a polling thread on one server."""
+    import torch
+    streams = stream_set(C)[:2]
+    devs = [torch.from_numpy(np.ascontiguousarray(fr)).cuda() for _, _, fr in streams]
+    torch.cuda.synchronize()
+    ref = [alone(C, p, d, 20) for (_, p, _), d in zip(streams, devs)]
+    masks = [torch.zeros((d.shape[0] - 20, p.width * p.height), dtype=torch.uint8, device="cuda")
+             for (_, p, _), d in zip(streams, devs)]
+    torch.cuda.synchronize()
+    srv = C.CogServer(hbm_budget=1 << 28, max_streams=4, depth=3)
+    ids = [srv.open(p, d[:20]) for (_, p, _), d in zip(streams, devs)]
+    got = []
+    stop = threading.Event()
+
+    def poller():
+        while not stop.is_set():
+            got.extend(srv.poll(wait_us=2000))
+
+    def submitter(i):
+        T = devs[i].shape[0] - 20
+        for f in range(T):
+            srv.submit(ids[i], devs[i][20 + f:21 + f], masks[i][f:f + 1], tag=i * 1000 + f)
+
+    th = [threading.Thread(target=poller)] + [threading.Thread(target=submitter, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th[1:]:
+        t.join()
+    srv.drain()
+    stop.set()
+    th[0].join()
+    got.extend(srv.poll())
+    assert len(got) == sum(d.shape[0] - 20 for d in devs)
+    states = [srv.export_state(s) for s in ids]
+    srv.close()
+    for i in range(2):
+        assert np.array_equal(masks[i].cpu().numpy(), ref[i][0])
+        assert states[i] == ref[i][1]
