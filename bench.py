@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-stream batched tick")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched tick")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving loop")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=150.0)
     return ap.parse_args()
 
 
@@ -122,6 +126,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batch_only:
         print(json.dumps({"batch": batch_leg(args, C)}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serve": serving_leg(args, C)}), flush=True)
         return
     spec = synth.preset(args.workload)
     P, T, N, K = spec.pixels, spec.frames, spec.n_train, spec.K
@@ -279,6 +286,9 @@ def main():
         del dev, masks
         torch.cuda.empty_cache()
         res["batch"] = batch_leg(args, C)
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        res["serve"] = serving_leg(args, C)
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(frames, spec, args.cpu_seconds)
@@ -444,6 +454,135 @@ def batch_leg(args, C):
         b.close()
         for c in ctxs:
             c.close()
+    return res
+
+
+# ---- serving loop: 256 camera streams, Poisson arrivals ---------------------------
+SERVE_WORKLOAD = "serve-256-poisson30"
+
+
+def serving_leg(args, C):
+    """256 stream requests over a run of serve_seconds: each asks to join at
+    a time in the first 40 % of the run (retrying every 100 ms while the HBM
+    budget is full), lives 40-90 % of the run, and submits frames at Poisson
+    times with a mean of 30 per second; resolutions cycle over 640x480,
+    1920x1080 and 3840x2160 (RGB u8, K=5) and foreground occupancy over 1, 5
+    and 10 %.  Streams of one (resolution, occupancy) share a device-resident
+    clip (100 training frames, then a ring of 32 frames played back and
+    forth).  Reports per-frame latency (submission to completion seen by the
+    host) and the aggregate pixel rate."""
+    import threading
+
+    import torch
+
+    from synth.device import DeviceScene
+
+    D = args.serve_seconds
+    N = 100
+    R2 = 2 * BATCH_RING
+    sizes = ((640, 480), (1920, 1080), (3840, 2160))
+    occs = (0.01, 0.05, 0.10)
+    t0 = time.time()
+    clips = {}
+    for si, (w, h) in enumerate(sizes):
+        for oi, occ in enumerate(occs):
+            sc = DeviceScene(w, h, 170509339 + 5 + 100 * si + 10 * oi, fg_occ=occ, n_rects=12)
+            tr = sc.frames(0, N).view(N, -1)
+            ring = sc.frames(N, BATCH_RING).view(BATCH_RING, -1)
+            clips[(si, oi)] = (tr, torch.cat([ring, ring.flip(0)]).contiguous())
+    torch.cuda.synchronize()
+    log(f"serve: clips generated in {time.time() - t0:.1f} s")
+    rng = np.random.default_rng(170509339 + 5)
+    reqs = []
+    for k in range(256):
+        si, oi = k % 3, (k // 3) % 3
+        start = float(rng.uniform(0.0, 0.4 * D))
+        life = float(rng.uniform(0.4 * D, 0.9 * D))
+        reqs.append(dict(si=si, oi=oi, start=start, end=min(D, start + life)))
+    events = []
+    for k, r in enumerate(reqs):
+        events.append((r["start"], 0, k))
+        t = r["start"]
+        while True:
+            t += float(rng.exponential(1.0 / 30.0))
+            if t >= r["end"]:
+                break
+            events.append((t, 1, k))
+        events.append((r["end"], 2, k))
+    events.sort()
+    # one mask frame per request (its submissions are in order, one frame each)
+    mask_bufs = [torch.empty(sizes[r["si"]][0] * sizes[r["si"]][1], dtype=torch.uint8, device="cuda")
+                 for r in reqs]
+    torch.cuda.synchronize()
+    params = {si: C.cog_default_params(w, h, 3, C.COG_U8, 5) for si, (w, h) in enumerate(sizes)}
+    srv = C.CogServer(hbm_budget=int(args.serve_budget_gb * 2**30), max_streams=256, depth=2)
+    comps = []
+    stop = threading.Event()
+
+    def poller():
+        while not stop.is_set():
+            comps.extend(srv.poll(max_n=4096, wait_us=5000))
+
+    pt = threading.Thread(target=poller)
+    pt.start()
+    ids, nsub, last_try = {}, {}, {}
+    fbytes = {si: w * h * 3 for si, (w, h) in enumerate(sizes)}
+    submitted = 0
+    dropped = 0
+    ts = time.perf_counter()
+    for t, kind, k in events:
+        while time.perf_counter() - ts < t:
+            pass
+        r = reqs[k]
+        if kind == 2:
+            if k in ids:
+                srv.close_stream(ids.pop(k))
+            continue
+        if k not in ids:
+            now = time.perf_counter() - ts
+            if kind == 1 and now - last_try.get(k, -1.0) < 0.1:
+                dropped += 1
+                continue
+            last_try[k] = now
+            try:
+                ids[k] = srv.open(params[r["si"]], clips[(r["si"], r["oi"])][0])
+                nsub[k] = 0
+            except C.CogError as e:
+                if e.status != C.COG_E_OOM:
+                    raise
+                dropped += kind
+                continue
+            if kind == 0:
+                continue
+        si = r["si"]
+        ring = clips[(si, r["oi"])][1]
+        f = nsub[k] % R2
+        srv.submit_ptr(ids[k], ring.data_ptr() + f * fbytes[si], mask_bufs[k].data_ptr(), tag=k)
+        nsub[k] += 1
+        submitted += 1
+    for k in list(ids):
+        srv.close_stream(ids.pop(k))
+    srv.drain()
+    wall = time.perf_counter() - ts
+    stop.set()
+    pt.join()
+    comps.extend(srv.poll(max_n=1 << 16))
+    st = srv.stats()
+    srv.close()
+    lat = np.array([c["t_done_us"] - c["t_submit_us"] for c in comps]) / 1e3
+    ok = all(c["status"] == 0 for c in comps)
+    res = {"workload": SERVE_WORKLOAD,
+           "streams": "256 requests; 640x480 / 1920x1080 / 3840x2160 RGB u8 K=5 cycling, "
+                      "foreground 1/5/10 %; Poisson arrivals, mean 30 frames/s per stream",
+           "seconds": round(wall, 3), "hbm_budget_gb": args.serve_budget_gb,
+           "admitted": st["streams_admitted"], "rejected_attempts": st["streams_rejected"],
+           "frames_submitted": submitted, "frames_completed": st["frames"],
+           "frames_not_admitted": dropped, "all_ok": ok,
+           "ticks": st["ticks"], "frames_per_tick": round(st["frames"] / max(1, st["ticks"]), 2),
+           "mpx_s": round(st["pixel_frames"] / wall / 1e6, 1),
+           "latency_p50_ms": round(pct(lat, 50), 3), "latency_p99_ms": round(pct(lat, 99), 3),
+           "latency_max_ms": round(float(lat.max()), 3)}
+    log(f"serve: {res}")
     return res
 
 

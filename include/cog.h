@@ -190,7 +190,7 @@ typedef struct {
   cog_ctx *ctx;           /* trained context, cascade path, 64-pixel tiles (tile_px 0 or 64) */
   const void *frames;     /* device: nframes x H x W x C, contiguous */
   uint8_t *masks;         /* device: nframes x H x W, or NULL */
-  int32_t nframes;        /* >= 0 (0: the item is skipped); <= 64 when infos is set */
+  int32_t nframes;        /* >= 0 (0: the item is skipped); <= 16 when infos is set */
   int32_t reserved;       /* must be 0 */
   cog_step_info *infos;   /* host array of nframes entries, or NULL */
 } cog_tick_item;
@@ -242,10 +242,13 @@ void cog_batch_destroy(cog_batch *b);
  * pending submission of every stream into one batched tick (continuous
  * batching: frames that arrive while a tick runs join the next one), so the
  * work of different requests overlaps on the device.  Every stream's state
- * stays resident in device memory from open to close; a stream is admitted
- * only if its state fits the HBM budget (state buffers of closed streams are
- * pooled and reused).  Each stream's masks and state are bit-identical to
- * the same frames run alone through cog_step_frames.
+ * stays resident in device memory from open to close; the HBM budget is
+ * reserved once at creation and a stream is admitted only if its state fits
+ * in a free range of it (ranges of closed streams are reused, neighbours
+ * merged), so serving never allocates or frees device memory.  A new
+ * stream trains on a side stream and its frames join ticks when that is
+ * done.  Each stream's masks and state are bit-identical to the same frames
+ * run alone through cog_step_frames.
  *
  * Threading: every call may come from any thread; calls are serialised by
  * the server.  Frames and masks are device buffers owned by the caller and
@@ -270,16 +273,17 @@ typedef struct {
   int64_t streams_admitted; /* cog_server_open successes */
   int64_t streams_rejected; /* cog_server_open refusals for lack of budget */
   int64_t bytes_budget;     /* device bytes the server may hold for stream state */
-  int64_t bytes_allocated;  /* held: open streams' state plus the reuse pool */
+  int64_t bytes_allocated;  /* reserved at creation (the budget, rounded to 256 B) */
   int64_t bytes_in_use;     /* open streams' state */
+  int64_t bytes_largest_free; /* largest contiguous free range of the reservation */
   int64_t pending;          /* submissions not yet issued */
   int64_t in_flight;        /* ticks issued and not yet complete */
 } cog_server_stats;
 
 /* Create a server on hip_stream (NULL: the server creates its own stream)
- * holding at most hbm_budget bytes of stream state and max_streams streams
- * (1..4096); depth = ticks in flight (1..8).  Errors: COG_E_INVALID,
- * COG_E_OOM, COG_E_DEVICE. */
+ * reserving hbm_budget bytes of device memory for stream state, for at most
+ * max_streams streams (1..4096); depth = ticks in flight (1..8).  Errors:
+ * COG_E_INVALID, COG_E_OOM (the budget cannot be reserved), COG_E_DEVICE. */
 cog_status cog_server_create(void *hip_stream, size_t hbm_budget, int32_t max_streams,
                              int32_t depth, cog_server **out);
 
@@ -298,8 +302,8 @@ cog_status cog_server_open(cog_server *s, const cog_params *p, const void *train
 cog_status cog_server_submit(cog_server *s, int32_t id, const void *frames, int32_t nframes,
                              uint8_t *masks, int64_t tag);
 
-/* Close stream id: its queued frames still complete; then its state buffer
- * returns to the pool.  COG_E_INVALID for an unknown id. */
+/* Close stream id: its queued frames still complete; then its state range
+ * returns to the reservation.  COG_E_INVALID for an unknown id. */
 cog_status cog_server_close(cog_server *s, int32_t id);
 
 /* Move up to max completions (oldest first) to out; *n receives the count.

@@ -82,7 +82,8 @@ class cog_completion(ct.Structure):
 class cog_server_stats(ct.Structure):
     _fields_ = [(f, ct.c_int64) for f in (
         "ticks", "frames", "pixel_frames", "streams_open", "streams_admitted", "streams_rejected",
-        "bytes_budget", "bytes_allocated", "bytes_in_use", "pending", "in_flight")]
+        "bytes_budget", "bytes_allocated", "bytes_in_use", "bytes_largest_free", "pending",
+        "in_flight")]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -145,7 +145,7 @@ cog_status plan_tick(cog_batch *b, const cog_tick_item *items, int32_t n, bool w
     if (it.nframes == 0) continue;
     if (!it.frames) return bfail(COG_E_INVALID, "frames is NULL");
     if (want_infos && it.infos) {
-      if (it.nframes > cog_rt::kChunk) return bfail(COG_E_INVALID, "at most 64 frames per item with infos");
+      if (it.nframes > cog_rt::kChunk) return bfail(COG_E_INVALID, "at most 16 frames per item with infos");
       any_infos = true;
     }
     const ClassKey key{h->plan.C, h->plan.K, h->p.dtype == COG_F32 ? 1 : 0};

@@ -12,7 +12,7 @@
 
 namespace cog_rt {
 
-constexpr int kChunk = 64;  // frames per launch when statistics are requested
+constexpr int kChunk = 16;  // frames per launch when statistics are requested
 
 // Device layout of one stream's state (all regions 256-byte aligned).
 struct Plan {

@@ -39,6 +39,7 @@ struct SStream {
   int64_t pixels = 0;
   bool closing = false;
   int in_flight = 0;  // submissions issued and not complete
+  hipEvent_t trained = nullptr;  // end of the training launch (until seen complete)
   std::deque<Submission> q;
 };
 
@@ -58,13 +59,59 @@ struct Tick {
 
 using Clock = std::chrono::steady_clock;
 
+// The budget is reserved as one device allocation at creation; stream states
+// are carved out of it (best fit, neighbours coalesced on release), so
+// admissions and departures never call hipMalloc or hipFree, which would
+// wait for the whole device.
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+
+  bool take(size_t n, size_t *off) {
+    auto best = free_.end();
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n && (best == free_.end() || it->second < best->second)) best = it;
+    if (best == free_.end()) return false;
+    *off = best->first;
+    const size_t rest = best->second - n;
+    free_.erase(best);
+    if (rest) free_[*off + n] = rest;
+    return true;
+  }
+
+  void give(size_t off, size_t n) {
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + n == nx->first) {
+      n += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
+
+  size_t largest() const {
+    size_t m = 0;
+    for (auto &kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+};
+
 }  // namespace
 
 struct cog_server {
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t train_stream = nullptr;  // admissions train here, beside the ticks
   int device = 0;
-  size_t budget = 0, allocated = 0, in_use = 0;
+  size_t budget = 0, in_use = 0;
+  int opening = 0;  // admissions reserved and not yet registered
   int32_t max_streams = 0;
   int depth = 2;
   cog_batch *batch = nullptr;
@@ -74,7 +121,7 @@ struct cog_server {
   std::condition_variable cv_work, cv_done;
   std::map<int32_t, SStream> streams;
   int32_t next_id = 0;
-  std::vector<std::pair<char *, size_t>> pool;  // reusable state buffers
+  Arena arena;
   std::deque<Tick> in_flight;
   std::vector<hipEvent_t> spare_events;
   std::deque<cog_completion> done;
@@ -97,18 +144,19 @@ double now_us(const cog_server *s) {
   return std::chrono::duration<double, std::micro>(Clock::now() - s->t0).count();
 }
 
-// Frees a finished stream's context (its state buffer goes to the pool).
+// Frees a finished stream's context (its state returns to the arena).
 // The context owns no device memory here and no work refers to it, so
 // nothing needs to wait.
 void finalize(cog_server *s, int32_t id) {
   auto it = s->streams.find(id);
   if (it == s->streams.end()) return;
   SStream &st = it->second;
+  if (st.trained) (void)hipEventDestroy(st.trained);
   if (st.ctx->own_state || st.ctx->stage_in || st.ctx->stage_mask)
     cog_destroy(st.ctx);
   else
     delete st.ctx;
-  s->pool.emplace_back(st.state, st.bytes);
+  s->arena.give((size_t)(st.state - s->arena.base), st.bytes);
   s->in_use -= st.bytes;
   s->streams.erase(it);
 }
@@ -144,13 +192,22 @@ void retire_front(cog_server *s, cog_status st) {
   s->cv_done.notify_all();
 }
 
+// Whether a stream's training has finished (its frames may join ticks).
+bool trained(SStream &st) {
+  if (!st.trained) return true;
+  if (hipEventQuery(st.trained) != hipSuccess) return false;
+  (void)hipEventDestroy(st.trained);
+  st.trained = nullptr;
+  return true;
+}
+
 // Gathers the oldest submission of every stream into one tick and issues it.
 bool issue_tick(cog_server *s) {
   std::vector<cog_tick_item> items;
   Tick t;
   for (auto &kv : s->streams) {
     SStream &st = kv.second;
-    if (st.q.empty()) continue;
+    if (st.q.empty() || !trained(st)) continue;
     const Submission &sub = st.q.front();
     cog_tick_item it{};
     it.ctx = st.ctx;
@@ -226,8 +283,12 @@ void scheduler_main(cog_server *s) {
       continue;
     }
     if (pending && (int)s->in_flight.size() < s->depth) {
-      issue_tick(s);
-      s->cv_flight.notify_one();
+      if (issue_tick(s)) {
+        s->cv_flight.notify_one();
+        continue;
+      }
+      // everything queued waits for its stream's training: look again soon
+      s->cv_work.wait_for(lk, std::chrono::microseconds(100));
       continue;
     }
     s->cv_work.wait(lk);
@@ -303,8 +364,22 @@ cog_status cog_server_create(void *hip_stream, size_t hbm_budget, int32_t max_st
     }
     s->own_stream = true;
   }
+  s->budget = (hbm_budget + 255) & ~(size_t)255;
+  if (hipMalloc((void **)&s->arena.base, s->budget) != hipSuccess) {
+    (void)hipGetLastError();
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return sfail(COG_E_OOM, "the HBM budget could not be reserved");
+  }
+  s->arena.size = s->budget;
+  s->arena.free_[0] = s->budget;
   cog_status rc = cog_batch_create(s->stream, max_streams, &s->batch);
+  if (rc == COG_OK && hipStreamCreateWithFlags(&s->train_stream, hipStreamNonBlocking) != hipSuccess) {
+    cog_batch_destroy(s->batch);
+    rc = sfail(COG_E_DEVICE, "stream creation failed");
+  }
   if (rc != COG_OK) {
+    (void)hipFree(s->arena.base);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return rc;
@@ -321,6 +396,8 @@ cog_status cog_server_create(void *hip_stream, size_t hbm_budget, int32_t max_st
     s->cv_flight.notify_all();
     if (s->completer.joinable()) s->completer.join();
     cog_batch_destroy(s->batch);
+    (void)hipStreamDestroy(s->train_stream);
+    (void)hipFree(s->arena.base);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return sfail(COG_E_OOM, "thread creation failed");
@@ -340,59 +417,55 @@ cog_status cog_server_open(cog_server *s, const cog_params *p, const void *train
   size_t bytes = 0;
   cog_status rc = cog_state_bytes(p, &bytes);
   if (rc != COG_OK) return rc;
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->sticky != COG_OK) return sfail(s->sticky, "server failed: " + s->sticky_msg);
-  if ((int32_t)s->streams.size() >= s->max_streams) {
-    s->rejected += 1;
-    return sfail(COG_E_OOM, "the server holds max_streams streams");
-  }
-  // a pooled buffer (smallest that fits), else a new one within the budget,
-  // releasing pooled buffers if that makes room
+  bytes = (bytes + 255) & ~(size_t)255;
   char *buf = nullptr;
-  size_t cap = 0;
-  int best = -1;
-  for (size_t i = 0; i < s->pool.size(); ++i)
-    if (s->pool[i].second >= bytes && (best < 0 || s->pool[i].second < s->pool[best].second)) best = (int)i;
-  if (best >= 0) {
-    buf = s->pool[best].first;
-    cap = s->pool[best].second;
-    s->pool.erase(s->pool.begin() + best);
-  } else {
-    if (s->in_use + bytes > s->budget) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->sticky != COG_OK) return sfail(s->sticky, "server failed: " + s->sticky_msg);
+    if ((int32_t)s->streams.size() + s->opening >= s->max_streams) {
+      s->rejected += 1;
+      return sfail(COG_E_OOM, "the server holds max_streams streams");
+    }
+    size_t off = 0;
+    if (!s->arena.take(bytes, &off)) {
       s->rejected += 1;
       return sfail(COG_E_OOM, "stream state does not fit the HBM budget");
     }
-    std::sort(s->pool.begin(), s->pool.end(),
-              [](const std::pair<char *, size_t> &a, const std::pair<char *, size_t> &b) { return a.second > b.second; });
-    while (s->allocated + bytes > s->budget && !s->pool.empty()) {
-      (void)hipFree(s->pool.back().first);
-      s->allocated -= s->pool.back().second;
-      s->pool.pop_back();
-    }
-    if (hipMalloc((void **)&buf, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      s->rejected += 1;
-      return sfail(COG_E_OOM, "state allocation failed");
-    }
-    cap = bytes;
-    s->allocated += bytes;
+    buf = s->arena.base + off;
+    s->in_use += bytes;
+    s->opening += 1;
   }
+  // Built without the server lock, so ticks keep flowing: the context is
+  // created and trained on the side stream (the weight upload waits only for
+  // that stream), and its frames join ticks once the training event has
+  // completed.
   cog_ctx *ctx = nullptr;
-  rc = cog_create(p, s->stream, buf, cap, &ctx);
+  hipEvent_t ev = nullptr;
+  rc = cog_create(p, s->train_stream, buf, bytes, &ctx);
   if (rc == COG_OK) rc = cog_train_prior(ctx, train_frames, n_train, 1);
+  if (rc == COG_OK && (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+                       hipEventRecord(ev, s->train_stream) != hipSuccess)) {
+    rc = COG_E_DEVICE;
+    (void)hipStreamSynchronize(s->train_stream);
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->opening -= 1;
   if (rc != COG_OK) {
-    std::string msg = cog_last_error(ctx);
+    std::string msg = ctx ? cog_last_error(ctx) : cog_last_error(nullptr);
+    if (ev) (void)hipEventDestroy(ev);
     if (ctx) delete ctx;
-    s->pool.emplace_back(buf, cap);
+    s->arena.give((size_t)(buf - s->arena.base), bytes);
+    s->in_use -= bytes;
     return sfail(rc, msg);
   }
+  ctx->stream = s->stream;
   const int32_t nid = s->next_id++;
   SStream &st = s->streams[nid];
+  st.trained = ev;
   st.ctx = ctx;
   st.state = buf;
-  st.bytes = cap;
+  st.bytes = bytes;
   st.pixels = (int64_t)p->width * p->height;
-  s->in_use += cap;
   s->admitted += 1;
   *id = nid;
   return COG_OK;
@@ -455,6 +528,8 @@ cog_status cog_server_export(cog_server *s, int32_t id, void *host_dst, size_t b
   if (s->sticky != COG_OK) return sfail(s->sticky, "server failed: " + s->sticky_msg);
   auto it = s->streams.find(id);
   if (it == s->streams.end()) return sfail(COG_E_INVALID, "no such open stream");
+  if (it->second.trained && hipEventSynchronize(it->second.trained) != hipSuccess)
+    return sfail(COG_E_DEVICE, "training failed");
   return cog_export_state(it->second.ctx, host_dst, bytes);
 }
 
@@ -469,8 +544,9 @@ cog_status cog_server_stats_get(cog_server *s, cog_server_stats *out) {
   out->streams_admitted = s->admitted;
   out->streams_rejected = s->rejected;
   out->bytes_budget = (int64_t)s->budget;
-  out->bytes_allocated = (int64_t)s->allocated;
+  out->bytes_allocated = (int64_t)s->arena.size;
   out->bytes_in_use = (int64_t)s->in_use;
+  out->bytes_largest_free = (int64_t)s->arena.largest();
   int64_t pend = 0;
   for (auto &kv : s->streams) pend += (int64_t)kv.second.q.size();
   out->pending = pend;
@@ -488,13 +564,15 @@ void cog_server_destroy(cog_server *s) {
   if (s->scheduler.joinable()) s->scheduler.join();
   if (s->completer.joinable()) s->completer.join();
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->train_stream);
   std::vector<int32_t> ids;
   for (auto &kv : s->streams) ids.push_back(kv.first);
   for (int32_t id : ids) finalize(s, id);
-  for (auto &b : s->pool) (void)hipFree(b.first);
+  (void)hipFree(s->arena.base);
   for (hipEvent_t e : s->spare_events)
     if (e) (void)hipEventDestroy(e);
   cog_batch_destroy(s->batch);
+  (void)hipStreamDestroy(s->train_stream);
   if (s->own_stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }
