@@ -29,6 +29,7 @@ struct orc_state {
   uint16_t *cnt;    /* [npix][3] */
   uint8_t *label;   /* [npix] previous label */
   float *prev;      /* [npix][C] previous frame value */
+  uint16_t *sat;    /* [npix] consecutive confident evaluated frames (sampling) */
   uint16_t W[NBINS][NLEVELS];
 };
 
@@ -192,6 +193,11 @@ static int params_ok(const orc_params *p) {
   if (!(p->kde_h > 0.0f)) return 0;
   if (!(p->res_e2 > 0.0f) || !(p->res_e1 <= p->res_e2)) return 0;
   if (!(p->lambda_m > 0.0f)) return 0;
+  if (p->stage_mask & ORC_SAMPLE) {
+    if (p->samp_window < 1 || p->samp_window > 65535) return 0;
+    if (p->samp_period < 1 || p->samp_period > 65535) return 0;
+    if (!(p->samp_lambda >= 0.0f)) return 0;
+  }
   return 1;
 }
 
@@ -209,7 +215,8 @@ orc_state *orc_create(const orc_params *p) {
   s->cnt = (uint16_t *)calloc((size_t)(P * 3), sizeof(uint16_t));
   s->label = (uint8_t *)calloc((size_t)P, 1);
   s->prev = (float *)calloc((size_t)(P * C), sizeof(float));
-  if (!s->gmm || !s->rga || !s->table || !s->cnt || !s->label || !s->prev ||
+  s->sat = (uint16_t *)calloc((size_t)P, sizeof(uint16_t));
+  if (!s->gmm || !s->rga || !s->table || !s->cnt || !s->label || !s->prev || !s->sat ||
       orc_kde_weights((double)p->kde_h, &s->W[0][0]) != 0) {
     orc_destroy(s);
     return NULL;
@@ -225,6 +232,7 @@ void orc_destroy(orc_state *s) {
   free(s->cnt);
   free(s->label);
   free(s->prev);
+  free(s->sat);
   free(s);
 }
 
@@ -290,10 +298,33 @@ int orc_train(orc_state *s, const void *frames, int n) {
     s->rga[px * (C + 1) + C] = comp[1 + C];
     s->label[px] = (uint8_t)lab;
     for (int c = 0; c < C; ++c) s->prev[px * C + c] = xp[c];
+    s->sat[px] = 0;
   }
   s->n_train = n;
   s->frame = n;
   return 0;
+}
+
+/* ---- confidence-based spatio-temporal sampling (§2 "Confidence based
+ * temporal sampling", §3.2): a pixel whose value stays in its dominant mode
+ * (decided by frame differencing, or by the running average within
+ * samp_lambda standard deviations) for samp_window evaluated frames has a
+ * saturated confidence.  Regions are blocks of ORC_BLOCK consecutive pixels:
+ * when every pixel of a block is saturated, the block's cascade updates are
+ * halted and it is sampled only on frames n with (n + block) divisible by
+ * samp_period (the phase is staggered over blocks); on the other frames each
+ * label is repeated and nothing adapts.  A pixel that is not confident on an
+ * evaluated frame loses its saturation, so its block is evaluated on every
+ * frame again. ------------------------------------------------------------- */
+static int block_skipped(const orc_state *s, int64_t blk) {
+  const orc_params *p = &s->p;
+  if (!(p->stage_mask & ORC_SAMPLE)) return 0;
+  if ((s->frame + blk) % p->samp_period == 0) return 0;
+  const int64_t b0 = blk * ORC_BLOCK;
+  const int64_t b1 = b0 + ORC_BLOCK < s->npix ? b0 + ORC_BLOCK : s->npix;
+  for (int64_t px = b0; px < b1; ++px)
+    if (s->sat[px] < p->samp_window) return 0;
+  return 1;
 }
 
 /* ---- one frame of the rejection cascade (§2 "Cascade of Gaussians CoG",
@@ -309,10 +340,22 @@ int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
   const float oar = 1.0f - p->alpha_rga;
   const float pden = (C == 3) ? 16581375.0f : 255.0f;  /* 255^C */
   const float nm1 = (float)(s->n_train - 1);
-  int64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, n3bg = 0, nfg = 0;
+  const float lam_s2 = p->samp_lambda * p->samp_lambda;
+  int64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, n3bg = 0, nfg = 0, nskip = 0;
+  int skip = 0;
 
   for (int64_t px = 0; px < P; ++px) {
+    if (px % ORC_BLOCK == 0) skip = block_skipped(s, px / ORC_BLOCK);
+    if (skip) {
+      /* halted: the label is repeated, no level runs, nothing adapts */
+      const int lab = s->label[px];
+      nskip++;
+      if (lab == ORC_FG) nfg++;
+      if (mask) mask[px] = lab == ORC_FG ? 255 : 0;
+      continue;
+    }
     float x[3];
+    int confident = 0;
     for (int c = 0; c < C; ++c) x[c] = load_x(p, frame, px, c);
     float *xp = s->prev + px * C;
     float *rg = s->rga + px * (C + 1);
@@ -324,6 +367,7 @@ int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
     if ((p->stage_mask & ORC_FD) && dl <= p->tau_fd) {
       lab = s->label[px];
       n0++;
+      confident = 1;
       goto done;
     }
     /* S1: running Gaussian average */
@@ -334,6 +378,7 @@ int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
     }
     if ((p->stage_mask & ORC_RGA) && dr2 <= lam_r2 * rg[C]) {
       lab = ORC_BG;
+      confident = dr2 <= lam_s2 * rg[C];
       for (int c = 0; c < C; ++c) rg[c] = oar * rg[c] + p->alpha_rga * x[c];
       float sr = 0.0f;
       for (int c = 0; c < C; ++c) {
@@ -382,6 +427,8 @@ int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
     if (mask) mask[px] = lab == ORC_FG ? 255 : 0;
     s->label[px] = (uint8_t)lab;
     for (int c = 0; c < C; ++c) xp[c] = x[c];
+    if (p->stage_mask & ORC_SAMPLE)
+      s->sat[px] = confident ? (uint16_t)(s->sat[px] < 65535 ? s->sat[px] + 1 : 65535) : 0;
   }
   if (info) {
     info[0] = s->frame;
@@ -392,6 +439,7 @@ int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
     info[5] = n3bg;
     info[6] = nfg;
     info[7] = ((double)n3 > (double)p->illum_frac * (double)P) ? 1 : 0;
+    info[8] = nskip;
   }
   s->frame++;
   return 0;
@@ -416,9 +464,9 @@ int orc_gmm_step(orc_state *s, const void *frame, uint8_t *mask) {
   return 0;
 }
 
-/* ---- canonical export: 64-byte header, then sections each padded to 64 B:
- * gmm f32[P][K][C+2], rga f32[P][C+1], table u8[P][C][16], cnt u16[P][3],
- * label u8[P], prev f32[P][C]. ---------------------------------------------- */
+/* ---- canonical export: 64-byte header (version 2), then sections each
+ * padded to 64 B: gmm f32[P][K][C+2], rga f32[P][C+1], table u8[P][C][16],
+ * cnt u16[P][3], label u8[P], prev f32[P][C], sat u16[P]. ------------------ */
 static size_t pad64(size_t n) { return (n + 63) & ~(size_t)63; }
 
 size_t orc_canonical_bytes(const orc_params *p) {
@@ -426,7 +474,7 @@ size_t orc_canonical_bytes(const orc_params *p) {
   const size_t P = (size_t)p->width * p->height;
   const size_t C = (size_t)p->channels, K = (size_t)p->K;
   return 64 + pad64(P * K * (C + 2) * 4) + pad64(P * (C + 1) * 4) + pad64(P * C * NBINS) +
-         pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4);
+         pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2);
 }
 
 int orc_export(const orc_state *s, void *dst, size_t bytes) {
@@ -437,7 +485,7 @@ int orc_export(const orc_state *s, void *dst, size_t bytes) {
   const size_t C = (size_t)p->channels, K = (size_t)p->K;
   char *o = (char *)dst;
   memset(o, 0, orc_canonical_bytes(p));
-  uint32_t hdr32[2] = {0x31474F43u, 1u};
+  uint32_t hdr32[2] = {0x31474F43u, 2u};
   int32_t hdri[6] = {p->width, p->height, p->channels, p->K, p->dtype, s->n_train};
   int64_t fr = s->frame;
   memcpy(o, hdr32, 8);
@@ -455,5 +503,7 @@ int orc_export(const orc_state *s, void *dst, size_t bytes) {
   memcpy(o + off, s->label, P);
   off += pad64(P);
   memcpy(o + off, s->prev, P * C * 4);
+  off += pad64(P * C * 4);
+  memcpy(o + off, s->sat, P * 2);
   return 0;
 }

@@ -25,7 +25,7 @@ extern "C" {
 #endif
 
 enum { ORC_U8 = 0, ORC_F32 = 1 };
-enum { ORC_FD = 1u, ORC_RGA = 2u, ORC_KDE = 4u };
+enum { ORC_FD = 1u, ORC_RGA = 2u, ORC_KDE = 4u, ORC_SAMPLE = 8u };
 enum { ORC_BG = 0, ORC_FG = 1 };
 
 typedef struct {
@@ -38,12 +38,17 @@ typedef struct {
   float kde_h, res_e1, res_e2;
   float lambda_m, conf_thr, p_null, kappa_alpha;
   float illum_frac;
+  /* confidence-based spatio-temporal sampling (stage bit ORC_SAMPLE) */
+  int32_t samp_window;      /* confident frames before a pixel saturates */
+  int32_t samp_period;      /* a saturated block is evaluated every samp_period frames */
+  float samp_lambda;        /* confidence gate of S1 decisions, in standard deviations */
 } orc_params;
 
 typedef struct orc_state orc_state;
 
-/* info[8] = {frame, n0, n1, n2, n3, n3_bg, n_fg, illum_flag} */
-enum { ORC_INFO_LEN = 8 };
+/* info[9] = {frame, n0, n1, n2, n3, n3_bg, n_fg, illum_flag, n_skip} */
+enum { ORC_INFO_LEN = 9 };
+enum { ORC_BLOCK = 64 };  /* pixels per sampling block (consecutive, row-major) */
 
 /* Integer kernel-weight table W[b][v] (16 bins x 256 levels), row-major. */
 int orc_kde_weights(double h, uint16_t *out);

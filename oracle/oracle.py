@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cog_oracle.c")
 LIB = os.path.join(HERE, "libcog_oracle.so")
 
-FD, RGA, KDE = 1, 2, 4
+FD, RGA, KDE, SAMPLE = 1, 2, 4, 8
 U8, F32 = 0, 1
 
 # Defaults of the readings taken where the paper gives no number (K, alpha,
@@ -31,6 +31,7 @@ DEFAULTS = dict(
     kde_h=8.0, res_e1=16.0, res_e2=48.0,
     lambda_m=None, conf_thr=0.5, p_null=0.1, kappa_alpha=0.5,
     illum_frac=0.7,
+    samp_window=32, samp_period=4, samp_lambda=None,
 )
 
 
@@ -46,6 +47,7 @@ class OrcParams(ct.Structure):
         ("lambda_m", ct.c_float), ("conf_thr", ct.c_float), ("p_null", ct.c_float),
         ("kappa_alpha", ct.c_float),
         ("illum_frac", ct.c_float),
+        ("samp_window", ct.c_int32), ("samp_period", ct.c_int32), ("samp_lambda", ct.c_float),
     ]
 
 
@@ -96,6 +98,8 @@ def make_params(width: int, height: int, channels: int = 3, K: int = 3, **kw) ->
         d["alpha_rga"] = d["alpha"]
     if d["lambda_m"] is None:
         d["lambda_m"] = 2.0 * d["lambda_rga"]
+    if d["samp_lambda"] is None:
+        d["samp_lambda"] = d["lambda_rga"]
     p = OrcParams()
     p.width, p.height, p.channels, p.K = width, height, channels, K
     for k, v in d.items():
@@ -167,10 +171,10 @@ class Oracle:
     def step(self, frame):
         a = self._frames(frame)
         mask = np.empty(self.npix, dtype=np.uint8)
-        info = (ct.c_int64 * 8)()
+        info = (ct.c_int64 * 9)()
         if lib().orc_step(self._h, a.ctypes.data, mask.ctypes.data, info) != 0:
             raise RuntimeError("orc_step failed")
-        keys = ("frame", "n0", "n1", "n2", "n3", "n3_bg", "n_fg", "illum_flag")
+        keys = ("frame", "n0", "n1", "n2", "n3", "n3_bg", "n_fg", "illum_flag", "n_skip")
         return mask, dict(zip(keys, list(info)))
 
     def gmm_step(self, frame):

@@ -303,7 +303,7 @@ cog_status cog_canonical_bytes(const cog_params *p, size_t *bytes) {
   if (!bytes) return fail(nullptr, COG_E_INVALID, "bytes is NULL");
   const size_t P = (size_t)p->width * p->height, C = (size_t)p->channels, K = (size_t)p->K;
   *bytes = 64 + pad64(P * K * (C + 2) * 4) + pad64(P * (C + 1) * 4) + pad64(P * C * 16) +
-           pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4);
+           pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2);
   return COG_OK;
 }
 
@@ -478,7 +478,7 @@ cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes) {
   const size_t P = (size_t)pl.P, C = (size_t)pl.C, K = (size_t)pl.K;
   char *o = static_cast<char *>(host_dst);
   std::memset(o, 0, need);
-  const uint32_t h32[2] = {kMagic, 1u};
+  const uint32_t h32[2] = {kMagic, 2u};
   const int32_t hi[6] = {h->p.width, h->p.height, h->p.channels, h->p.K, h->p.dtype, h->n_train};
   std::memcpy(o, h32, 8);
   std::memcpy(o + 8, hi, 24);
@@ -532,17 +532,23 @@ cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes) {
 cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
   if (!h) return fail(nullptr, COG_E_INVALID, "context is NULL");
   if (!host_src) return fail(h, COG_E_INVALID, "host_src is NULL");
+  if (bytes < 64) return fail(h, COG_E_INVALID, "buffer smaller than a canonical header");
+  const char *in = static_cast<const char *>(host_src);
+  uint32_t ver = 0;
+  std::memcpy(&ver, in + 4, 4);
   size_t need = 0;
   cog_canonical_bytes(&h->p, &need);
-  if (bytes < need) return fail(h, COG_E_INVALID, "buffer smaller than cog_canonical_bytes()");
-  const char *in = static_cast<const char *>(host_src);
+  // version 1 has no saturation section
+  if (ver == 1u) need -= pad64((size_t)h->plan.P * 2);
+  if (bytes < need) return fail(h, COG_E_INVALID, "buffer smaller than the canonical state");
   uint32_t h32[2];
   int32_t hi[6];
   int64_t frame;
   std::memcpy(h32, in, 8);
   std::memcpy(hi, in + 8, 24);
   std::memcpy(&frame, in + 32, 8);
-  if (h32[0] != kMagic || h32[1] != 1u) return fail(h, COG_E_INVALID, "not a canonical state");
+  if (h32[0] != kMagic || (h32[1] != 1u && h32[1] != 2u))
+    return fail(h, COG_E_INVALID, "not a canonical state");
   if (hi[0] != h->p.width || hi[1] != h->p.height || hi[2] != h->p.channels || hi[3] != h->p.K ||
       hi[4] != h->p.dtype)
     return fail(h, COG_E_INVALID, "state shape does not match the context");

@@ -114,14 +114,33 @@ class Brute:
             self.cnt.append(cnt)
             self.label.append(lab)
             self.prev.append(list(xs[-1]))
+        self.sat = [0] * self.P
+        self.frame = N
 
     # -- cascade ----------------------------------------------------------------
+    def halted(self, blk):
+        """Sampling: a block of 64 pixels whose pixels all have a saturated
+        confidence is evaluated only when (frame + block) % period == 0."""
+        p = self.p
+        if not (p["stage_mask"] & 8) or (self.frame + blk) % p["samp_period"] == 0:
+            return False
+        pix = range(64 * blk, min(self.P, 64 * blk + 64))
+        return all(self.sat[q] >= p["samp_window"] for q in pix)
+
     def step(self, frame):
-        """frame: [P, C] ints.  Returns (mask list, stages list, margins list)."""
+        """frame: [P, C] ints.  Returns (mask list, stages list, margins list);
+        stage -1 marks a pixel of a halted block."""
         p, C = self.p, self.C
         sm = p["stage_mask"]
         masks, stages, margins = [], [], []
+        halted = [self.halted(b) for b in range((self.P + 63) // 64)]
         for px in range(self.P):
+            if halted[px // 64]:
+                masks.append(255 if self.label[px] else 0)
+                stages.append(-1)
+                margins.append(float("inf"))
+                continue
+            confident = False
             x = [float(frame[px][c]) for c in range(C)]
             xp = self.prev[px]
             mu_r, var_r = self.rga[px]
@@ -129,11 +148,16 @@ class Brute:
             dl = max(abs(x[c] - xp[c]) for c in range(C))
             if (sm & 1) and dl <= p["tau_fd"]:
                 lab, st = self.label[px], 0
+                confident = True
             else:
                 dr2 = sum((x[c] - mu_r[c]) ** 2 for c in range(C))
                 margin = min(margin, abs(dr2 - p["lambda_rga"] ** 2 * var_r) / max(1.0, dr2))
                 if (sm & 2) and dr2 <= p["lambda_rga"] ** 2 * var_r:
                     lab, st = 0, 1
+                    if sm & 8:
+                        ls2 = p["samp_lambda"] ** 2 * var_r
+                        confident = dr2 <= ls2
+                        margin = min(margin, abs(dr2 - ls2) / max(1.0, dr2))
                     ar = p["alpha_rga"]
                     mu_r = [(1 - ar) * mu_r[c] + ar * x[c] for c in range(C)]
                     s = sum((x[c] - mu_r[c]) ** 2 for c in range(C))
@@ -166,7 +190,10 @@ class Brute:
                             self.rga[px] = [list(self.comp[px][mp][1]), self.comp[px][mp][2]]
             self.label[px] = lab
             self.prev[px] = x
+            if sm & 8:
+                self.sat[px] = min(self.sat[px] + 1, 65535) if confident else 0
             masks.append(255 if lab else 0)
             stages.append(st)
             margins.append(margin)
+        self.frame += 1
         return masks, stages, margins
