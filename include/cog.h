@@ -56,7 +56,8 @@ enum {
   COG_STAGE_FD = 1u,   /* S0: consistent hypothesis propagation (frame difference) */
   COG_STAGE_RGA = 2u,  /* S1: running Gaussian average */
   COG_STAGE_KDE = 4u,  /* S2: scene-prior confidence */
-  COG_STAGE_ALL = 7u
+  COG_STAGE_ALL = 7u,
+  COG_STAGE_SAMPLE = 8u /* confidence-based spatio-temporal sampling (off by default) */
 };
 
 /* Which kernel family a context runs. */
@@ -93,6 +94,17 @@ typedef struct {
   float illum_frac;        /* illumination flag when n3 > illum_frac*pixels [0.7] */
   int32_t path;            /* cog_path [COG_PATH_CASCADE] */
   int32_t tile_px;         /* cascade pixels per tile: 0 (auto = 64), 64, 128, 256, 512, 1024 */
+  /* Confidence-based spatio-temporal sampling (§2 "Confidence based temporal
+   * sampling", §3.2), enabled by COG_STAGE_SAMPLE: a pixel decided by frame
+   * differencing, or by the running average within samp_lambda standard
+   * deviations, on samp_window consecutive evaluated frames has a saturated
+   * confidence; a block of 64 consecutive pixels that are all saturated is
+   * evaluated only on frames n with (n + block) % samp_period == 0, and on
+   * the other frames its labels repeat and nothing adapts.  Cascade path
+   * with 64-pixel tiles only. */
+  int32_t samp_window;     /* 1..65535 [32] */
+  int32_t samp_period;     /* 1..65535 [4] */
+  float samp_lambda;       /* >= 0 [lambda_rga] */
 } cog_params;
 
 /* Per-frame statistics (the occupancy of the cascade levels, §2 "Cascade of
@@ -103,7 +115,7 @@ typedef struct {
   int64_t n3_bg;        /* of those, labelled background by the mixture */
   int64_t n_fg;         /* foreground pixels in the mask */
   int32_t illum_flag;   /* n_stage[3] > illum_frac * pixels */
-  int32_t reserved;
+  int32_t n_skip;       /* pixels of blocks halted by sampling (no level ran) */
 } cog_step_info;
 
 /* Fill *p with the defaults above for a w x h stream of c channels.
@@ -153,11 +165,13 @@ cog_status cog_reset(cog_ctx *h);
 void cog_destroy(cog_ctx *h);
 
 /* Canonical, layout-independent state: a 64-byte header {u32 magic 'COG1',
- * u32 version 1, i32 width, height, channels, K, dtype, n_train, i64 frame},
+ * u32 version 2, i32 width, height, channels, K, dtype, n_train, i64 frame},
  * then sections each padded to 64 bytes: gmm f32[P][K][C+2] (w, mu[C], var in
  * rank order), rga f32[P][C+1] (mu_r[C], var_r), table u8[P][C][16],
- * cnt u16[P][3], label u8[P] (0/1), prev f32[P][C].  For checkpoint/resume
- * and tests; synchronous; host buffers only. */
+ * cnt u16[P][3], label u8[P] (0/1), prev f32[P][C], sat u16[P] (sampling
+ * counters; version 2 of the layout; version-1 states, without that section,
+ * are still imported with zero counters).  For checkpoint/resume and tests;
+ * synchronous; host buffers only. */
 cog_status cog_canonical_bytes(const cog_params *p, size_t *bytes);
 cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes);
 cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libcog.so")
 
 COG_OK, COG_E_INVALID, COG_E_OOM, COG_E_STATE, COG_E_DEVICE, COG_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 COG_U8, COG_F32 = 0, 1
-COG_STAGE_FD, COG_STAGE_RGA, COG_STAGE_KDE, COG_STAGE_ALL = 1, 2, 4, 7
+COG_STAGE_FD, COG_STAGE_RGA, COG_STAGE_KDE, COG_STAGE_ALL, COG_STAGE_SAMPLE = 1, 2, 4, 7, 8
 COG_PATH_CASCADE, COG_PATH_GMM = 0, 1
 
 STATUS_NAMES = {0: "COG_OK", -1: "COG_E_INVALID", -2: "COG_E_OOM", -3: "COG_E_STATE",
@@ -40,18 +40,20 @@ class cog_params(ct.Structure):
         ("lambda_m", ct.c_float), ("conf_thr", ct.c_float), ("p_null", ct.c_float),
         ("kappa_alpha", ct.c_float), ("illum_frac", ct.c_float),
         ("path", ct.c_int32), ("tile_px", ct.c_int32),
+        ("samp_window", ct.c_int32), ("samp_period", ct.c_int32), ("samp_lambda", ct.c_float),
     ]
 
 
 class cog_step_info(ct.Structure):
     _fields_ = [
         ("frame", ct.c_int64), ("n_stage", ct.c_int64 * 4), ("n3_bg", ct.c_int64),
-        ("n_fg", ct.c_int64), ("illum_flag", ct.c_int32), ("reserved", ct.c_int32),
+        ("n_fg", ct.c_int64), ("illum_flag", ct.c_int32), ("n_skip", ct.c_int32),
     ]
 
     def as_dict(self) -> dict:
         return dict(frame=self.frame, n0=self.n_stage[0], n1=self.n_stage[1], n2=self.n_stage[2],
-                    n3=self.n_stage[3], n3_bg=self.n3_bg, n_fg=self.n_fg, illum_flag=self.illum_flag)
+                    n3=self.n_stage[3], n3_bg=self.n3_bg, n_fg=self.n_fg, illum_flag=self.illum_flag,
+                    n_skip=self.n_skip)
 
 
 class cog_tick_item(ct.Structure):

@@ -53,7 +53,7 @@ void fill_infos(const cog_ctx *h, int64_t first_frame, int n, const uint32_t *bl
     o.n3_bg = s[4];
     o.n_fg = s[5];
     o.illum_flag = ((double)s[3] > (double)h->p.illum_frac * (double)h->plan.P) ? 1 : 0;
-    o.reserved = 0;
+    o.n_skip = (int32_t)s[6];
   }
 }
 
@@ -78,7 +78,13 @@ std::string check_params(const cog_params *p) {
   if (!(p->T > 0.0f && p->T <= 1.0f)) return "T must be in (0, 1]";
   if (!(p->lambda > 0.0f)) return "lambda must be positive";
   if (!(p->var_min > 0.0f) || !(p->var_init >= p->var_min)) return "need 0 < var_min <= var_init";
-  if (p->stage_mask & ~7u) return "unknown stage_mask bits";
+  if (p->stage_mask & ~15u) return "unknown stage_mask bits";
+  if (p->stage_mask & COG_STAGE_SAMPLE) {
+    if (p->path != COG_PATH_CASCADE) return "sampling is a cascade option";
+    if (p->samp_window < 1 || p->samp_window > 65535) return "samp_window must be in [1, 65535]";
+    if (p->samp_period < 1 || p->samp_period > 65535) return "samp_period must be in [1, 65535]";
+    if (!(p->samp_lambda >= 0.0f)) return "samp_lambda must be >= 0";
+  }
   if (!(p->tau_fd >= 0.0f)) return "tau_fd must be >= 0";
   if (!(p->lambda_rga >= 0.0f)) return "lambda_rga must be >= 0";
   if (!(p->alpha_rga > 0.0f && p->alpha_rga <= 1.0f)) return "alpha_rga must be in (0, 1]";
@@ -128,6 +134,8 @@ Plan make_plan(const cog_params *p) {
   if (cascade) off += align256((size_t)pl.Ppad * pl.PB);
   pl.off_cnt = off;
   if (cascade) off += align256((size_t)pl.Ppad * 8);
+  pl.off_sat = off;
+  if (cascade) off += align256((size_t)pl.Ppad * 2);
   pl.off_prev = off;
   off += align256((size_t)pl.Ppad * pl.C * pl.sin);
   pl.off_labels = off;
@@ -182,6 +190,9 @@ cog::KParams make_kparams(const cog_params *p, int32_t n_train) {
   k.in_lo = p->in_lo;
   k.q_scale = 256.0f / (p->in_hi - p->in_lo);
   k.stage_mask = p->stage_mask;
+  k.samp_window = (uint32_t)(p->samp_window > 0 ? p->samp_window : 1);
+  k.samp_period = (uint32_t)(p->samp_period > 0 ? p->samp_period : 1);
+  k.lam_s2 = p->samp_lambda * p->samp_lambda;
   return k;
 }
 
@@ -222,6 +233,7 @@ cog_status run_frames(cog_ctx *h, const void *dframes, int n, uint8_t *dmasks, b
     fr.partials = want_stats ? reinterpret_cast<uint32_t *>(h->dstate + pl.off_partials) : nullptr;
     fr.nslots = pl.nslots;
     fr.nframes = cnt;
+    fr.frame0 = h->frame + done;
     hipError_t e;
     if (h->p.path == COG_PATH_CASCADE)
       e = cog::launch_cascade(pl.C, pl.K, h->p.dtype == COG_F32, pl.tile, h->buf, fr, h->kp,
@@ -286,6 +298,9 @@ cog_status cog_default_params(cog_params *p, int32_t w, int32_t h, int32_t c, in
   p->illum_frac = 0.7f;
   p->path = COG_PATH_CASCADE;
   p->tile_px = 0;
+  p->samp_window = 32;
+  p->samp_period = 4;
+  p->samp_lambda = p->lambda_rga;
   return COG_OK;
 }
 
@@ -320,6 +335,8 @@ cog_status cog_create(const cog_params *p, void *hip_stream, void *device_state,
   *out = nullptr;
   const std::string e = check_params(p);
   if (!e.empty()) return fail(nullptr, COG_E_INVALID, e);
+  if ((p->stage_mask & COG_STAGE_SAMPLE) && p->tile_px != 0 && p->tile_px != 64)
+    return fail(nullptr, COG_E_UNSUPPORTED, "sampling runs with 64-pixel tiles only");
   const Plan pl = make_plan(p);
   if (device_state && (reinterpret_cast<uintptr_t>(device_state) & 255))
     return fail(nullptr, COG_E_INVALID, "device_state must be 256-byte aligned");
@@ -355,6 +372,7 @@ cog_status cog_create(const cog_params *p, void *hip_stream, void *device_state,
   h->buf.prev = h->dstate + pl.off_prev;
   h->buf.labels = reinterpret_cast<unsigned long long *>(h->dstate + pl.off_labels);
   h->buf.kdew = reinterpret_cast<const uint16_t *>(h->dstate + pl.off_kdew);
+  h->buf.sat = reinterpret_cast<uint16_t *>(h->dstate + pl.off_sat);
   h->buf.P = pl.P;
 
   // prior kernel weights, uploaded level-major [256][16]
@@ -526,6 +544,8 @@ cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes) {
     if (pl.sin == 1) pv[i] = (float)reinterpret_cast<const uint8_t *>(raw.data() + pl.off_prev)[i];
     else pv[i] = reinterpret_cast<const float *>(raw.data() + pl.off_prev)[i];
   }
+  off += pad64(P * C * 4);
+  if (aos) std::memcpy(o + off, raw.data() + pl.off_sat, P * 2);
   return COG_OK;
 }
 
@@ -610,6 +630,8 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
       reinterpret_cast<float *>(raw.data() + pl.off_prev)[i] = pv[i];
     }
   }
+  off += pad64(P * C * 4);
+  if (aos && ver >= 2u) std::memcpy(raw.data() + pl.off_sat, in + off, P * 2);
   hipError_t e = hipMemcpyAsync(h->dstate, raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "state upload");

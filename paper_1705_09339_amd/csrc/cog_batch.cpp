@@ -27,13 +27,20 @@ constexpr int kMaxClasses = 8;     // classes in one tick
 constexpr int kMaxGraphs = 64;     // cached graph executables
 constexpr int kMaxItemsLimit = 4096;
 
+// A class of streams shares one kernel instantiation: channels, K, input
+// type, and whether sampling is on.  Schedules are set per (C, K, f32).
 struct ClassKey {
-  int C, K, f32;
+  int C, K, f32, samp;
   bool operator<(const ClassKey &o) const {
-    return std::tie(C, K, f32) < std::tie(o.C, o.K, o.f32);
+    return std::tie(C, K, f32, samp) < std::tie(o.C, o.K, o.f32, o.samp);
   }
-  bool operator==(const ClassKey &o) const { return C == o.C && K == o.K && f32 == o.f32; }
+  ClassKey sched_key() const { return ClassKey{C, K, f32, 0}; }
 };
+
+ClassKey class_of(const cog_ctx *h) {
+  return ClassKey{h->plan.C, h->plan.K, h->p.dtype == COG_F32 ? 1 : 0,
+                  (h->p.stage_mask & COG_STAGE_SAMPLE) ? 1 : 0};
+}
 
 // One class's launch in a tick.
 struct Launch {
@@ -73,7 +80,7 @@ struct cog_batch {
   size_t dstat_cap = 0;      // u32 words
   std::vector<uint32_t> hstat;
   std::map<ClassKey, cog_schedule> sched;
-  std::map<std::tuple<int, int, int, int>, int> occ;
+  std::map<std::tuple<int, int, int, int, int>, int> occ;
   std::vector<GraphEntry> graphs;
   uint64_t use_clock = 0;
 };
@@ -111,10 +118,10 @@ std::string check_schedule(const cog_schedule *s) {
 }
 
 int occupancy(cog_batch *b, const ClassKey &k, bool lp) {
-  const auto key = std::make_tuple(k.C, k.K, k.f32, lp ? 1 : 0);
+  const auto key = std::make_tuple(k.C, k.K, k.f32, k.samp, lp ? 1 : 0);
   auto it = b->occ.find(key);
   if (it != b->occ.end()) return it->second;
-  int n = cog::tick_blocks_per_cu(k.C, k.K, k.f32 != 0, lp);
+  int n = cog::tick_blocks_per_cu(k.C, k.K, k.f32 != 0, lp, k.samp != 0);
   if (n < 1) n = 1;
   b->occ[key] = n;
   return n;
@@ -148,7 +155,7 @@ cog_status plan_tick(cog_batch *b, const cog_tick_item *items, int32_t n, bool w
       if (it.nframes > cog_rt::kChunk) return bfail(COG_E_INVALID, "at most 16 frames per item with infos");
       any_infos = true;
     }
-    const ClassKey key{h->plan.C, h->plan.K, h->p.dtype == COG_F32 ? 1 : 0};
+    const ClassKey key = class_of(h);
     auto p = pos.find(key);
     if (p == pos.end()) {
       if ((int)pos.size() == kMaxClasses) return bfail(COG_E_INVALID, "more than 8 classes in one tick");
@@ -165,18 +172,17 @@ cog_status plan_tick(cog_batch *b, const cog_tick_item *items, int32_t n, bool w
   for (auto &kv : pos) launches[kv.second].key = kv.first;
   for (int i = 0; i < n; ++i) {
     if (items[i].nframes == 0) continue;
-    const cog_ctx *h = items[i].ctx;
-    const ClassKey key{h->plan.C, h->plan.K, h->p.dtype == COG_F32 ? 1 : 0};
+    const ClassKey key = class_of(items[i].ctx);
     Launch &L = launches[pos[key]];
     L.items.push_back(i);
-    L.tiles += h->plan.ntiles;
+    L.tiles += items[i].ctx->plan.ntiles;
   }
   for (Launch &L : launches) {
     if (L.tiles > 0x7fffffff) return bfail(COG_E_INVALID, "a tick's class exceeds 2^31 tiles");
     int minf = 1 << 30;
     for (int i : L.items) minf = std::min(minf, items[i].nframes);
     L.lp = minf >= 8;
-    auto sit = b->sched.find(L.key);
+    auto sit = b->sched.find(L.key.sched_key());
     const cog_schedule s = sit == b->sched.end() ? default_schedule() : sit->second;
     L.group = s.group;
     L.graph = s.use_graph != 0;
@@ -205,7 +211,7 @@ cog::TickItem *region_items(cog_batch *b, char *base, int j) {
 cog_status launch_all(cog_batch *b, const std::vector<Launch> &launches) {
   for (size_t j = 0; j < launches.size(); ++j) {
     const Launch &L = launches[j];
-    hipError_t e = cog::launch_tick(L.key.C, L.key.K, L.key.f32 != 0, L.lp,
+    hipError_t e = cog::launch_tick(L.key.C, L.key.K, L.key.f32 != 0, L.lp, L.key.samp != 0,
                                     region_head(b, b->ddesc, (int)j),
                                     region_items(b, b->ddesc, (int)j), L.grid, L.dynamic,
                                     b->stream);
@@ -221,6 +227,7 @@ cog_status run_graph(cog_batch *b, const std::vector<Launch> &launches) {
     key.push_back(L.key.C);
     key.push_back(L.key.K);
     key.push_back(L.key.f32);
+    key.push_back(L.key.samp);
     key.push_back(L.lp);
     key.push_back(L.grid);
     key.push_back(L.dynamic);
@@ -295,6 +302,7 @@ cog_status execute(cog_batch *b, const cog_tick_item *items, const std::vector<L
       d.fr.partials = want ? reinterpret_cast<uint32_t *>(h->dstate + h->plan.off_partials) : nullptr;
       d.fr.nslots = h->plan.nslots;
       d.fr.nframes = it.nframes;
+      d.fr.frame0 = h->frame;
       d.b = h->buf;
       d.kp = h->kp;
       d.tile_begin = tb;
@@ -423,7 +431,7 @@ cog_status cog_batch_set_schedule(cog_batch *b, int32_t channels, int32_t K, int
   if (!m.empty()) return bfail(COG_E_INVALID, m);
   if ((channels != 1 && channels != 3) || K < 1 || K > 8 || (dtype != COG_U8 && dtype != COG_F32))
     return bfail(COG_E_INVALID, "no such class");
-  b->sched[ClassKey{channels, K, dtype == COG_F32 ? 1 : 0}] = *s;
+  b->sched[ClassKey{channels, K, dtype == COG_F32 ? 1 : 0, 0}] = *s;
   return COG_OK;
 }
 
@@ -432,7 +440,7 @@ cog_status cog_batch_get_schedule(cog_batch *b, int32_t channels, int32_t K, int
   if (!b || !s) return bfail(COG_E_INVALID, "NULL argument");
   if ((channels != 1 && channels != 3) || K < 1 || K > 8 || (dtype != COG_U8 && dtype != COG_F32))
     return bfail(COG_E_INVALID, "no such class");
-  auto it = b->sched.find(ClassKey{channels, K, dtype == COG_F32 ? 1 : 0});
+  auto it = b->sched.find(ClassKey{channels, K, dtype == COG_F32 ? 1 : 0, 0});
   *s = it == b->sched.end() ? default_schedule() : it->second;
   return COG_OK;
 }
@@ -480,8 +488,8 @@ cog_status cog_batch_autotune(cog_batch *b, const cog_tick_item *items, int32_t 
     for (int g : {1, 4, 16}) cand.push_back(cog_schedule{bpc, 0, g, 1});
 
   for (size_t j = 0; j < launches.size() && s == COG_OK; ++j) {
-    const ClassKey key = launches[j].key;
-    const int occ_lim = occupancy(b, key, launches[j].lp);
+    const ClassKey key = launches[j].key.sched_key();
+    const int occ_lim = occupancy(b, launches[j].key, launches[j].lp);
     float best_ms = 1e30f;
     cog_schedule best_s = default_schedule();
     auto it0 = b->sched.find(key);

@@ -9,7 +9,8 @@ namespace cog {
 constexpr int kNT = 256;        // threads per workgroup (4 wave64)
 constexpr int kNW = kNT / 64;   // waves per workgroup
 constexpr int kBins = 16;       // prior bins per channel
-constexpr int kStat = 8;        // counters per statistics slot
+constexpr int kStat = 8;        // counters per statistics slot:
+                                // n0, n1, n2, n3, n3_bg, n_fg, n_skip, unused
 
 // Floats per per-pixel mixture record: {w[K], var[K], mu[K][C]} padded to 16 B.
 __host__ __device__ constexpr int rec_floats(int C, int K) { return ((K * (C + 2)) + 3) & ~3; }
@@ -27,6 +28,8 @@ struct KParams {
   float nm1;            // n_train - 1
   float in_lo, q_scale; // f32 input quantisation: floor((v - in_lo) * q_scale)
   uint32_t stage_mask;
+  uint32_t samp_window, samp_period;  // sampling: saturation window, evaluation period
+  float lam_s2;                       // sampling: confidence gate squared
 };
 
 // Device state of one stream (see the host planner for sizes).
@@ -38,6 +41,7 @@ struct Buffers {
   void *prev;                  // C values per pixel (u8 or f32, as the input)
   unsigned long long *labels;  // 1 bit per pixel, bit p&63 of word p>>6
   const uint16_t *kdew;        // prior kernel weights, level-major [256][16]
+  uint16_t *sat;               // sampling: consecutive confident frames per pixel
   int64_t P;
 };
 
@@ -50,6 +54,7 @@ struct Frames {
   uint32_t *partials;  // [nframes][nslots][kStat] or nullptr
   int nslots;
   int nframes;
+  int64_t frame0;      // index of frame 0 in the stream (sampling phase)
 };
 
 // ---- batched tick ------------------------------------------------------------
@@ -95,8 +100,8 @@ hipError_t launch_gmm(int C, int K, bool f32in, const Buffers &b, const Frames &
 // Persistent tick over one class (C, K, input type) of streams: grid
 // workgroups of one wave; dynamic = 0 deals units round-robin by workgroup,
 // 1 hands them out from head->queue.
-hipError_t launch_tick(int C, int K, bool f32in, bool lp, TickHead *head, const TickItem *items,
-                       int grid, int dynamic, hipStream_t s);
+hipError_t launch_tick(int C, int K, bool f32in, bool lp, bool samp, TickHead *head,
+                       const TickItem *items, int grid, int dynamic, hipStream_t s);
 // Statistics reduction: one job by value, or n jobs from a device table
 // (grid covers max_blocks x max_frames x n).
 hipError_t launch_stats(const StatJob &job, hipStream_t s);
@@ -104,6 +109,6 @@ hipError_t launch_stats_table(const StatJob *jobs, int n, int max_blocks, int ma
                               hipStream_t s);
 // Workgroups of the class's tick kernel one compute unit keeps resident
 // (0 if the query fails).
-int tick_blocks_per_cu(int C, int K, bool f32in, bool lp);
+int tick_blocks_per_cu(int C, int K, bool f32in, bool lp, bool samp);
 
 }  // namespace cog

@@ -570,6 +570,7 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
 #pragma unroll
       for (int c = 0; c < C; ++c) rg[c] = m.mu[0][c];
       rg[C] = m.var[0];
+      b.sat[p] = 0;  // no confident frame yet (sampling)
     }
     if constexpr (aos) rec_store<C, K>(b.gmm + p * rec_floats(C, K), m);
     else grp_store<C, K>(b.gmm, p, m);
@@ -1203,7 +1204,7 @@ struct TileLds {
 // The cascade over fr.nframes frames for the 64 pixels of one tile (tile =
 // index of the 64-pixel run within the stream), one pixel per lane.  Shared
 // by the one-stream kernel and the batched tick.
-template <int C, int K, bool F32, bool LP>
+template <int C, int K, bool F32, bool LP, bool SAMP>
 __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr, const KParams &kp,
                                              int64_t tile, int lane, TileLds<C, F32, LP> &lds) {
   constexpr int R = rec_floats(C, K);
@@ -1243,6 +1244,14 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
       for (int q = 0; q < PB / 16; ++q) s_prior[lane * (PB / 16) + q] = src[q];
     }
   }
+  // sampling (§2 "Confidence based temporal sampling"): the lane's count of
+  // consecutive confident frames (lanes past the end count as saturated) and
+  // the block's phase (frame + block) % period for frame 0
+  uint32_t sat = 0xffffu, ph = 0u;
+  if constexpr (SAMP) {
+    if (valid) sat = b.sat[p];
+    ph = (uint32_t)((fr.frame0 + tile) % (int64_t)kp.samp_period);
+  }
   // a lane reads back only its own staged record, so no wave-level sync is needed
   const uint8_t *prec = LP ? reinterpret_cast<const uint8_t *>(&s_prior[lane * (PB / 16)])
                            : b.prior + pcl * PB;
@@ -1279,6 +1288,23 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
     int mis = (mis0 + f0 * mis_step) & 3;
 
     for (int k = 0; k < nk; ++k, mis = (mis + mis_step) & 3) {
+      if constexpr (SAMP) {
+        // a block whose pixels are all saturated is evaluated only in phase
+        const bool halted = ph != 0u && __ballot(sat < kp.samp_window) == 0ull;
+        ph = ph + 1u == kp.samp_period ? 0u : ph + 1u;
+        if (halted) {
+          // the labels repeat; no level runs and nothing adapts
+          __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(lab ? 255 : 0), mr, moff,
+                                               k * (int)fr.mstride, 2);
+          if (fr.partials) {
+            const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
+            const uint32_t csk = (uint32_t)__popcll(__ballot(valid));
+            const uint32_t v = lane == 5 ? cfg : lane == 6 ? csk : 0u;
+            __builtin_amdgcn_raw_buffer_store_b32(v, sr, soff, k * srow, 0);
+          }
+          continue;
+        }
+      }
       float x[C];
       Stage::read_mis(s_in, k, mis, lane, x);
 
@@ -1294,6 +1320,14 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
       }
       const bool s0 = fd_on && dl <= kp.tau_fd;
       const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * rvar;
+      if constexpr (SAMP) {
+        // confident: decided by the frame difference, or by the running
+        // average within samp_lambda standard deviations (its variance before
+        // this frame's update)
+        const bool conf = s0 || (s1 && dr2 <= kp.lam_s2 * rvar);
+        const uint32_t nsat = conf ? (sat < 65535u ? sat + 1u : 65535u) : 0u;
+        sat = valid ? nsat : sat;
+      }
       {
         float nmu[C];
 #pragma unroll
@@ -1384,19 +1418,20 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
       rg[C] = rvar;
     }
     store_px<C, F32>(b.prev, p, xp);
+    if constexpr (SAMP) b.sat[p] = (uint16_t)sat;
   }
   const unsigned long long bal = __ballot(valid && lab);
   if (lane == 0) b.labels[tile0 >> 6] = bal;
 }
 
-template <int C, int K, bool F32, bool LP>
+template <int C, int K, bool F32, bool LP, bool SAMP>
 __global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
   __shared__ TileLds<C, F32, LP> lds;
   // Tiles follow the workgroup order, which the dispatcher deals round-robin
   // over the XCDs: the spatially clustered survivor work (foreground, bimodal
   // regions) is spread evenly over the chip.  (Contiguous tile runs per XCD
   // share boundary cache lines but concentrate that work; measured slower.)
-  cascade_tile<C, K, F32, LP>(b, fr, kp, blockIdx.x, threadIdx.x, lds);
+  cascade_tile<C, K, F32, LP, SAMP>(b, fr, kp, blockIdx.x, threadIdx.x, lds);
 }
 
 // ============================================================================
@@ -1431,7 +1466,7 @@ __device__ __forceinline__ int take_unit(uint32_t *queue, int lane) {
 }
 
 // Tile and unit indices are 32-bit: the host keeps a tick below 2^31 tiles.
-template <int C, int K, bool F32, bool LP>
+template <int C, int K, bool F32, bool LP, bool SAMP>
 __global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_tick(TickHead *head,
                                                                       const TickItem *items,
                                                                       int dynamic) {
@@ -1454,7 +1489,7 @@ __global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_tick(TickHead 
       const Frames fr = const_copy(&items[it].fr);
       const Buffers b = const_copy(&items[it].b);
       const KParams kp = const_copy(&items[it].kp);
-      cascade_tile<C, K, F32, LP>(b, fr, kp, t - (int)ci[it].tile_begin, lane, lds);
+      cascade_tile<C, K, F32, LP, SAMP>(b, fr, kp, t - (int)ci[it].tile_begin, lane, lds);
     }
     u = nxt;
   }
@@ -1609,16 +1644,25 @@ hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, 
   const unsigned g = grid_for(b.P, tile);
   // the prior goes to LDS when a launch covers enough frames to amortise it
   const bool lp = fr.nframes >= 8;
+  // sampling runs in the 64-pixel kernel only (the host rejects other tiles)
+  const bool samp = (kp.stage_mask & 8u) != 0;
+  if (samp && tile != 64) return hipErrorInvalidValue;
 #define COG_CASC(KK, CC, FF, PP, LL) \
   hipLaunchKernelGGL((k_cascade<CC, KK, FF, PP, LL>), dim3(g), dim3(kNT), 0, s, b, fr, kp)
 #define COG_CASCW(KK, CC, FF, PP, LL) \
   hipLaunchKernelGGL((k_cascade_w<CC, KK, FF, PP, LL>), dim3(g), dim3(64), 0, s, b, fr, kp)
-#define COG_CASCD(KK, CC, FF, LL) \
-  hipLaunchKernelGGL((k_cascade_d<CC, KK, FF, LL>), dim3(g), dim3(64), 0, s, b, fr, kp)
+#define COG_CASCD(KK, CC, FF, LL, SS) \
+  hipLaunchKernelGGL((k_cascade_d<CC, KK, FF, LL, SS>), dim3(g), dim3(64), 0, s, b, fr, kp)
 #define COG_CASC_TILE(CC, FF)                                                   \
   switch (tile * 2 + (lp ? 1 : 0)) {                                           \
-    case 128: { COG_K_CASES(COG_CASCD, CC, FF, false) } break;                 \
-    case 129: { COG_K_CASES(COG_CASCD, CC, FF, true) } break;                  \
+    case 128:                                                                  \
+      if (samp) { COG_K_CASES(COG_CASCD, CC, FF, false, true) }                \
+      else { COG_K_CASES(COG_CASCD, CC, FF, false, false) }                    \
+      break;                                                                   \
+    case 129:                                                                  \
+      if (samp) { COG_K_CASES(COG_CASCD, CC, FF, true, true) }                 \
+      else { COG_K_CASES(COG_CASCD, CC, FF, true, false) }                     \
+      break;                                                                   \
     case 256: { COG_K_CASES(COG_CASCW, CC, FF, 2, false) } break;              \
     case 257: { COG_K_CASES(COG_CASCW, CC, FF, 2, true) } break;               \
     case 512: { COG_K_CASES(COG_CASC, CC, FF, 1, false) } break;               \
@@ -1641,13 +1685,19 @@ hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, 
   return hipGetLastError();
 }
 
-hipError_t launch_tick(int C, int K, bool f32in, bool lp, TickHead *head, const TickItem *items,
-                       int grid, int dynamic, hipStream_t s) {
+hipError_t launch_tick(int C, int K, bool f32in, bool lp, bool samp, TickHead *head,
+                       const TickItem *items, int grid, int dynamic, hipStream_t s) {
   if (grid <= 0) return hipErrorInvalidValue;
-#define COG_TICK(KK, CC, FF, LL) \
-  hipLaunchKernelGGL((k_tick<CC, KK, FF, LL>), dim3(grid), dim3(64), 0, s, head, items, dynamic)
-#define COG_TICK_LP(CC, FF) \
-  if (lp) { COG_K_CASES(COG_TICK, CC, FF, true) } else { COG_K_CASES(COG_TICK, CC, FF, false) }
+#define COG_TICK(KK, CC, FF, LL, SS) \
+  hipLaunchKernelGGL((k_tick<CC, KK, FF, LL, SS>), dim3(grid), dim3(64), 0, s, head, items, dynamic)
+#define COG_TICK_LP(CC, FF)                                                          \
+  if (lp) {                                                                          \
+    if (samp) { COG_K_CASES(COG_TICK, CC, FF, true, true) }                          \
+    else { COG_K_CASES(COG_TICK, CC, FF, true, false) }                              \
+  } else {                                                                           \
+    if (samp) { COG_K_CASES(COG_TICK, CC, FF, false, true) }                         \
+    else { COG_K_CASES(COG_TICK, CC, FF, false, false) }                             \
+  }
   if (C == 3 && !f32in) { COG_TICK_LP(3, false) }
   else if (C == 3 && f32in) { COG_TICK_LP(3, true) }
   else if (C == 1 && !f32in) { COG_TICK_LP(1, false) }
@@ -1658,14 +1708,20 @@ hipError_t launch_tick(int C, int K, bool f32in, bool lp, TickHead *head, const 
   return hipGetLastError();
 }
 
-int tick_blocks_per_cu(int C, int K, bool f32in, bool lp) {
+int tick_blocks_per_cu(int C, int K, bool f32in, bool lp, bool samp) {
   if (K < 1 || K > 8) return 0;
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
-#define COG_OCC(KK, CC, FF, LL) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tick<CC, KK, FF, LL>, 64, 0)
-#define COG_OCC_LP(CC, FF) \
-  if (lp) { COG_K_CASES(COG_OCC, CC, FF, true) } else { COG_K_CASES(COG_OCC, CC, FF, false) }
+#define COG_OCC(KK, CC, FF, LL, SS) \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tick<CC, KK, FF, LL, SS>, 64, 0)
+#define COG_OCC_LP(CC, FF)                                                           \
+  if (lp) {                                                                          \
+    if (samp) { COG_K_CASES(COG_OCC, CC, FF, true, true) }                           \
+    else { COG_K_CASES(COG_OCC, CC, FF, true, false) }                               \
+  } else {                                                                           \
+    if (samp) { COG_K_CASES(COG_OCC, CC, FF, false, true) }                          \
+    else { COG_K_CASES(COG_OCC, CC, FF, false, false) }                              \
+  }
   if (C == 3 && !f32in) { COG_OCC_LP(3, false) }
   else if (C == 3 && f32in) { COG_OCC_LP(3, true) }
   else if (C == 1 && !f32in) { COG_OCC_LP(1, false) }

@@ -35,7 +35,8 @@ def orc_params_like(p):
         stage_mask=p.stage_mask, tau_fd=p.tau_fd, lambda_rga=p.lambda_rga,
         alpha_rga=p.alpha_rga, kde_h=p.kde_h, res_e1=p.res_e1, res_e2=p.res_e2,
         lambda_m=p.lambda_m, conf_thr=p.conf_thr, p_null=p.p_null,
-        kappa_alpha=p.kappa_alpha, illum_frac=p.illum_frac)
+        kappa_alpha=p.kappa_alpha, illum_frac=p.illum_frac, samp_window=p.samp_window,
+        samp_period=p.samp_period, samp_lambda=p.samp_lambda)
 
 
 def run_gpu(C, p, frames, n_train, mode="step", infos=True, stream=None):

@@ -79,11 +79,14 @@ def test_default_params(C):
     assert p.stage_mask == 7 and p.kde_bins == 16 and p.lambda_m == 5.0
     assert (p.res_e1, p.res_e2, p.conf_thr, p.p_null, p.kappa_alpha) == (16, 48, 0.5, np.float32(0.1), 0.5)
     assert p.illum_frac == np.float32(0.7) and p.path == C.COG_PATH_CASCADE
+    assert (p.samp_window, p.samp_period, p.samp_lambda) == (32, 4, 2.5)
 
 
 @pytest.mark.parametrize("bad", [
     dict(K=0), dict(K=9), dict(channels=2), dict(width=0), dict(var_min=0.0),
-    dict(var_init=1.0), dict(kde_bins=8), dict(stage_mask=8), dict(tile_px=384),
+    dict(var_init=1.0), dict(kde_bins=8), dict(stage_mask=16), dict(tile_px=384),
+    dict(stage_mask=15, samp_window=0), dict(stage_mask=15, samp_period=0),
+    dict(stage_mask=15, samp_lambda=-1.0), dict(stage_mask=8, path=1),
     dict(path=2), dict(alpha=0.0), dict(res_e1=60.0), dict(dtype=1, in_lo=1.0, in_hi=1.0),
     dict(struct_size=4),
 ])
