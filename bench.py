@@ -135,16 +135,18 @@ def main():
     F = T - N
     log(f"workload {spec.name}: {spec.width}x{spec.height} x {T} frames, N={N}, K={K}")
     t0 = time.time()
-    frames = synth.make_stream(spec)
+    frames, gt = synth.make_stream(spec, with_gt=True)
     log(f"generated in {time.time() - t0:.1f} s")
     dev = torch.from_numpy(frames).cuda()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     masks = torch.empty((F, P), dtype=torch.uint8, device="cuda")
 
-    def make(path):
+    def make(path, sample=False):
         p = C.cog_default_params(spec.width, spec.height, 3, C.COG_U8, K, path=path,
                                  tile_px=args.tile)
+        if sample:
+            p.stage_mask = C.COG_STAGE_ALL | C.COG_STAGE_SAMPLE
         return C.CogStream(p, stream=stream)
 
     chunk = args.chunk or F
@@ -187,6 +189,7 @@ def main():
 
     cog_ctx = make(C.COG_PATH_CASCADE)
     wall, tr_ms, ca_ms = timed(cog_ctx, "cog")
+    acc = {"cascade": accuracy(masks, gt[N:])}
     # level occupancy of the same stream, taken through the 128-pixel tile
     # kernel (identical results for every tile size) so that the timed
     # kernel's launches all cover the same frame count
@@ -199,6 +202,38 @@ def main():
 
     gmm_ctx = make(C.COG_PATH_GMM)
     g_wall, g_tr_ms, g_ca_ms = timed(gmm_ctx, "gmm")
+    acc["gmm"] = accuracy(masks, gt[N:])
+
+    # the sampling variant (§2 "Confidence based temporal sampling"), its
+    # agreement with the plain cascade and its halted share
+    samp = {}
+    if not args.tile or args.tile == 64:
+        cas_masks = None
+        cog_ctx.reset()
+        cog_ctx.train_prior(dev[:N])
+        cog_ctx.step_frames(dev[N:], masks)
+        cas_masks = masks.cpu().numpy()
+        s_ctx = make(C.COG_PATH_CASCADE, sample=True)
+        s_wall, s_tr_ms, s_ca_ms = timed(s_ctx, "cog+sampling")
+        s_masks = masks.cpu().numpy()
+        acc["cascade_sampling"] = accuracy(masks, gt[N:])
+        s_ctx.reset()
+        s_ctx.train_prior(dev[:N])
+        s_inf = []
+        for t0_ in range(0, F, 16):
+            s_inf += s_ctx.step_frames(dev[N + t0_:N + min(F, t0_ + 16)], None, want_info=True)
+        s_ctx.close()
+        sp = C.cog_default_params(spec.width, spec.height, 3, C.COG_U8, K)
+        samp = {"value": round(P * T * args.steps / s_wall / 1e6, 1),
+                "ms_per_step": round(s_wall / args.steps * 1e3, 4),
+                "online_mpx_s": round(P * F / (s_ca_ms * 1e-3) / 1e6, 1),
+                "speedup_vs_gmm": round((P * T * args.steps / s_wall) / (P * T * args.steps / g_wall), 3),
+                "speedup_vs_gmm_online": round(g_ca_ms / s_ca_ms, 3),
+                "halted_frac": round(sum(i["n_skip"] for i in s_inf) / (P * F), 4),
+                "mask_diff_vs_cascade": round(float((s_masks != cas_masks).mean()), 5),
+                "samp_window": sp.samp_window, "samp_period": sp.samp_period,
+                "samp_lambda": round(sp.samp_lambda, 3)}
+        log(f"sampling: {samp}")
 
     # per-frame streaming: one cog_step per frame, latency submit -> mask ready
     lat = {}
@@ -280,6 +315,8 @@ def main():
         "occupancy": {k: round(v / (P * F), 5) for k, v in occ.items()},
         "latency": lat,
         "roofline": roof,
+        "sampling": samp,
+        "accuracy_vs_ground_truth": acc,
     }
 
     if not args.no_batch:
@@ -584,6 +621,18 @@ def serving_leg(args, C):
            "latency_max_ms": round(float(lat.max()), 3)}
     log(f"serve: {res}")
     return res
+
+
+def accuracy(masks_dev, gt):
+    """Foreground detection against the generator's ground truth (the union
+    of the moving objects): per-pixel error rate and F1 of the foreground.
+    Context only: the bimodal background regions count as background."""
+    m = masks_dev.cpu().numpy().reshape(gt.shape) != 0
+    tp = int(np.logical_and(m, gt).sum())
+    fp = int(np.logical_and(m, ~gt).sum())
+    fn = int(np.logical_and(~m, gt).sum())
+    f1 = 2 * tp / max(1, 2 * tp + fp + fn)
+    return {"error_rate": round((fp + fn) / gt.size, 5), "f1": round(f1, 4)}
 
 
 def cpu_baseline(frames, spec, budget_s):

@@ -1288,109 +1288,104 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
     int mis = (mis0 + f0 * mis_step) & 3;
 
     for (int k = 0; k < nk; ++k, mis = (mis + mis_step) & 3) {
+      bool halted = false;
       if constexpr (SAMP) {
-        // a block whose pixels are all saturated is evaluated only in phase
-        const bool halted = ph != 0u && __ballot(sat < kp.samp_window) == 0ull;
+        // a block whose pixels are all saturated is evaluated only in phase;
+        // when halted the labels repeat, no level runs and nothing adapts
+        halted = ph != 0u && __ballot(sat < kp.samp_window) == 0ull;
         ph = ph + 1u == kp.samp_period ? 0u : ph + 1u;
-        if (halted) {
-          // the labels repeat; no level runs and nothing adapts
-          __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(lab ? 255 : 0), mr, moff,
-                                               k * (int)fr.mstride, 2);
-          if (fr.partials) {
-            const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
-            const uint32_t csk = (uint32_t)__popcll(__ballot(valid));
-            const uint32_t v = lane == 5 ? cfg : lane == 6 ? csk : 0u;
-            __builtin_amdgcn_raw_buffer_store_b32(v, sr, soff, k * srow, 0);
-          }
-          continue;
-        }
       }
-      float x[C];
-      Stage::read_mis(s_in, k, mis, lane, x);
+      int st = -1;
+      if (!halted) {
+        float x[C];
+        Stage::read_mis(s_in, k, mis, lane, x);
 
-      // S0 (frame difference) and S1 (running average) for every lane
-      float dl = 0.0f;
+        // S0 (frame difference) and S1 (running average) for every lane
+        float dl = 0.0f;
 #pragma unroll
-      for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xp[c]));
-      float dr2 = 0.0f;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const float d = x[c] - rmu[c];
-        dr2 = dr2 + d * d;
-      }
-      const bool s0 = fd_on && dl <= kp.tau_fd;
-      const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * rvar;
-      if constexpr (SAMP) {
-        // confident: decided by the frame difference, or by the running
-        // average within samp_lambda standard deviations (its variance before
-        // this frame's update)
-        const bool conf = s0 || (s1 && dr2 <= kp.lam_s2 * rvar);
-        const uint32_t nsat = conf ? (sat < 65535u ? sat + 1u : 65535u) : 0u;
-        sat = valid ? nsat : sat;
-      }
-      {
-        float nmu[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) nmu[c] = kp.one_m_alpha_rga * rmu[c] + kp.alpha_rga * x[c];
-        float sr = 0.0f;
+        for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xp[c]));
+        float dr2 = 0.0f;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const float e = x[c] - nmu[c];
-          sr = sr + e * e;
+          const float d = x[c] - rmu[c];
+          dr2 = dr2 + d * d;
         }
-        const float nvar = fmaxf(kp.var_min, kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr);
+        const bool s0 = fd_on && dl <= kp.tau_fd;
+        const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * rvar;
+        if constexpr (SAMP) {
+          // confident: decided by the frame difference, or by the running
+          // average within samp_lambda standard deviations (its variance before
+          // this frame's update)
+          const bool conf = s0 || (s1 && dr2 <= kp.lam_s2 * rvar);
+          const uint32_t nsat = conf ? (sat < 65535u ? sat + 1u : 65535u) : 0u;
+          sat = valid ? nsat : sat;
+        }
+        {
+          float nmu[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) rmu[c] = s1 ? nmu[c] : rmu[c];
-        rvar = s1 ? nvar : rvar;
-      }
-      dirty |= s1 ? 1u : 0u;
-      lab = s1 ? 0u : lab;
-      int st = !valid ? -1 : (s0 ? 0 : (s1 ? 1 : 3));
+          for (int c = 0; c < C; ++c) nmu[c] = kp.one_m_alpha_rga * rmu[c] + kp.alpha_rga * x[c];
+          float sr = 0.0f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const float e = x[c] - nmu[c];
+            sr = sr + e * e;
+          }
+          const float nvar = fmaxf(kp.var_min, kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr);
+#pragma unroll
+          for (int c = 0; c < C; ++c) rmu[c] = s1 ? nmu[c] : rmu[c];
+          rvar = s1 ? nvar : rvar;
+        }
+        dirty |= s1 ? 1u : 0u;
+        lab = s1 ? 0u : lab;
+        st = !valid ? -1 : (s0 ? 0 : (s1 ? 1 : 3));
 
-      if (valid && !s0 && !s1) {
-        // survivor: first time in this launch, the mixture record is
-        // requested before S2 runs
-        if (!have_rec) {
-          rec_load<C, K>(grec, m);
-          have_rec = 1u;
-        }
-        float conf = 0.0f;
-        bool accept = false;
-        if (kde_on) {
-          conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
-          accept = conf >= kp.conf_thr;
-        }
-        if (accept) {
-          st = 2;  // S2: background by the scene prior, nothing adapts
-          lab = 0u;
-        } else {
-          // S3: the full mixture with the confidence-driven rate
-          const float ae = kp.alpha * (1.0f - kp.kappa * conf);
-          int l, mp;
-          mix_step<C, K>(m, x, ae, kp, l, mp);
-          rec_dirty = 1u;
-          lab = l ? 1u : 0u;
-          if (!l) {
-            // background from the mixture: the running average takes the
-            // matched component (the transition update of the active level)
-            float sv = m.var[0];
+        if (valid && !s0 && !s1) {
+          // survivor: first time in this launch, the mixture record is
+          // requested before S2 runs
+          if (!have_rec) {
+            rec_load<C, K>(grec, m);
+            have_rec = 1u;
+          }
+          float conf = 0.0f;
+          bool accept = false;
+          if (kde_on) {
+            conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
+            accept = conf >= kp.conf_thr;
+          }
+          if (accept) {
+            st = 2;  // S2: background by the scene prior, nothing adapts
+            lab = 0u;
+          } else {
+            // S3: the full mixture with the confidence-driven rate
+            const float ae = kp.alpha * (1.0f - kp.kappa * conf);
+            int l, mp;
+            mix_step<C, K>(m, x, ae, kp, l, mp);
+            rec_dirty = 1u;
+            lab = l ? 1u : 0u;
+            if (!l) {
+              // background from the mixture: the running average takes the
+              // matched component (the transition update of the active level)
+              float sv = m.var[0];
 #pragma unroll
-            for (int c = 0; c < C; ++c) rmu[c] = m.mu[0][c];
+              for (int c = 0; c < C; ++c) rmu[c] = m.mu[0][c];
 #pragma unroll
-            for (int kk = 1; kk < K; ++kk) {
-              if (mp == kk) {
-                sv = m.var[kk];
+              for (int kk = 1; kk < K; ++kk) {
+                if (mp == kk) {
+                  sv = m.var[kk];
 #pragma unroll
-                for (int c = 0; c < C; ++c) rmu[c] = m.mu[kk][c];
+                  for (int c = 0; c < C; ++c) rmu[c] = m.mu[kk][c];
+                }
               }
+              rvar = sv;
+              dirty = 1u;
             }
-            rvar = sv;
-            dirty = 1u;
           }
         }
-      }
 #pragma unroll
-      for (int c = 0; c < C; ++c) xp[c] = x[c];
+        for (int c = 0; c < C; ++c) xp[c] = x[c];
+      } else {
+        st = valid ? 4 : -1;  // halted by sampling
+      }
       // masks are streamed out: non-temporal (cache policy bit 1)
       __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(lab ? 255 : 0), mr, moff,
                                            k * (int)fr.mstride, 2);
@@ -1401,8 +1396,9 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
         const uint32_t c3 = (uint32_t)__popcll(__ballot(st == 3));
         const uint32_t c3bg = (uint32_t)__popcll(__ballot(st == 3 && !lab));
         const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
+        const uint32_t csk = SAMP ? (uint32_t)__popcll(__ballot(st == 4)) : 0u;
         const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
-                         : lane == 4 ? c3bg : lane == 5 ? cfg : 0u;
+                         : lane == 4 ? c3bg : lane == 5 ? cfg : lane == 6 ? csk : 0u;
         __builtin_amdgcn_raw_buffer_store_b32(v, sr, soff, k * srow, 0);
       }
     }
@@ -1424,8 +1420,15 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
   if (lane == 0) b.labels[tile0 >> 6] = bal;
 }
 
+// Waves per SIMD the one-wave cascade kernels are held to: five for u8 input
+// up to K=5 (at most 96 VGPRs, every wave of a 640x480 frame resident); the
+// sampling variant's extra live state needs the 128-VGPR budget of four.
+__host__ __device__ constexpr int cascade_min_waves(bool f32, int K, bool samp) {
+  return (!f32 && K <= 5) ? (samp ? 4 : 5) : 1;
+}
+
 template <int C, int K, bool F32, bool LP, bool SAMP>
-__global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
+__global__ __launch_bounds__(64, cascade_min_waves(F32, K, SAMP)) void k_cascade_d(Buffers b, Frames fr, KParams kp) {
   __shared__ TileLds<C, F32, LP> lds;
   // Tiles follow the workgroup order, which the dispatcher deals round-robin
   // over the XCDs: the spatially clustered survivor work (foreground, bimodal
@@ -1467,7 +1470,7 @@ __device__ __forceinline__ int take_unit(uint32_t *queue, int lane) {
 
 // Tile and unit indices are 32-bit: the host keeps a tick below 2^31 tiles.
 template <int C, int K, bool F32, bool LP, bool SAMP>
-__global__ __launch_bounds__(64, (!F32 && K <= 5) ? 5 : 1) void k_tick(TickHead *head,
+__global__ __launch_bounds__(64, cascade_min_waves(F32, K, SAMP)) void k_tick(TickHead *head,
                                                                       const TickItem *items,
                                                                       int dynamic) {
   __shared__ TileLds<C, F32, LP> lds;
