@@ -481,6 +481,19 @@ __device__ __forceinline__ float confidence(const uint8_t *rec, const float (&x)
 //  - the mixture warm-up (initialised from frame 0, stepped on 1..N-1).
 // Then the max-normalised u8 table, counts, mixture, running average (from
 // the dominant mode), previous frame and label are written once.
+// floor((255 a + floor(d / 2)) / d) for 0 <= a <= d, d > 0, exactly.  The
+// quotient is at most 255: a binary32 estimate is within one of it (its
+// relative error is below 2^-22), and two exact 64-bit comparisons correct it,
+// instead of a full 64-bit integer division.
+__device__ __forceinline__ uint32_t round_ratio255(uint32_t a, uint32_t d) {
+  const uint64_t num = 255ull * a + (d >> 1);
+  int32_t q = (int32_t)((float)num / (float)d);
+  q = q < 0 ? 0 : (q > 255 ? 255 : q);
+  if ((uint64_t)(uint32_t)q * d > num) --q;
+  if ((uint64_t)(uint32_t)(q + 1) * d <= num) ++q;
+  return (uint32_t)q;
+}
+
 template <int C, int K, bool F32, bool PRIOR>
 __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, int64_t stride,
                                                int n, KParams kp) {
@@ -502,12 +515,19 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
 #pragma unroll
       for (int q = 0; q < kBins; ++q) acc[c][q] = 0u;
     uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
-    float x[C], xp[C];
+    float x[C], xp[C], xn[C];
     Mix<C, K> m;
     load_px<C, F32>(frames, p, x);
     mix_init<C, K>(m, x, kp.var_init);
+    // the next frame's value is requested one frame ahead, so its latency
+    // overlaps the current frame's work
+    if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
     for (int j = 0; j < n; ++j) {
-      load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j), p, x);
+      if (j >= 1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = xn[c];
+        if (j + 1 < n) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
+      }
       if constexpr (with_prior) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -548,8 +568,7 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
         for (int q = 0; q < kBins; ++q) amax = acc[c][q] > amax ? acc[c][q] : amax;
 #pragma unroll
         for (int q = 0; q < kBins; ++q) {
-          const uint32_t t =
-              amax ? (uint32_t)((255ull * acc[c][q] + (amax >> 1)) / amax) : 0u;
+          const uint32_t t = amax ? round_ratio255(acc[c][q], amax) : 0u;
           const int byte = c * kBins + q;
           words[byte >> 2] |= (t & 0xffu) << (8 * (byte & 3));
         }
