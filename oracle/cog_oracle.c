@@ -30,6 +30,7 @@ struct orc_state {
   uint8_t *label;   /* [npix] previous label */
   float *prev;      /* [npix][C] previous frame value */
   uint16_t *sat;    /* [npix] consecutive confident evaluated frames (sampling) */
+  float *feat;      /* [npix][4] warm-up sums of the dominant slot: S_v, Q_v, S_w, Q_w */
   uint16_t W[NBINS][NLEVELS];
 };
 
@@ -216,7 +217,8 @@ orc_state *orc_create(const orc_params *p) {
   s->label = (uint8_t *)calloc((size_t)P, 1);
   s->prev = (float *)calloc((size_t)(P * C), sizeof(float));
   s->sat = (uint16_t *)calloc((size_t)P, sizeof(uint16_t));
-  if (!s->gmm || !s->rga || !s->table || !s->cnt || !s->label || !s->prev || !s->sat ||
+  s->feat = (float *)calloc((size_t)P * 4, sizeof(float));
+  if (!s->gmm || !s->rga || !s->table || !s->cnt || !s->label || !s->prev || !s->sat || !s->feat ||
       orc_kde_weights((double)p->kde_h, &s->W[0][0]) != 0) {
     orc_destroy(s);
     return NULL;
@@ -233,6 +235,7 @@ void orc_destroy(orc_state *s) {
   free(s->label);
   free(s->prev);
   free(s->sat);
+  free(s->feat);
   free(s);
 }
 
@@ -255,6 +258,7 @@ int orc_train(orc_state *s, const void *frames, int n) {
     float *comp = s->gmm + px * K * F;
     float x[3], xp[3];
     int lab = ORC_BG;
+    float sv = 0.0f, qv = 0.0f, sw = 0.0f, qw = 0.0f;
 
     /* mixture initialisation from the first frame: one component with a
      * high initial variance, the others inactive */
@@ -277,6 +281,13 @@ int orc_train(orc_state *s, const void *frames, int n) {
         int bin = dl < p->res_e1 ? 0 : (dl < p->res_e2 ? 1 : 2);
         cnt[bin] += 1;
         orc_pixel_gmmstep(p, comp, x, p->alpha, &lab, NULL);
+        /* adapted variance and weight of the dominant (rank-0) component,
+         * observed after every warm-up step (grouping features) */
+        const float v = comp[1 + C], w = comp[0];
+        sv = sv + v;
+        qv = qv + v * v;
+        sw = sw + w;
+        qw = qw + w * w;
       }
       for (int c = 0; c < C; ++c) xp[c] = x[c];
     }
@@ -299,6 +310,10 @@ int orc_train(orc_state *s, const void *frames, int n) {
     s->label[px] = (uint8_t)lab;
     for (int c = 0; c < C; ++c) s->prev[px * C + c] = xp[c];
     s->sat[px] = 0;
+    s->feat[px * 4 + 0] = sv;
+    s->feat[px * 4 + 1] = qv;
+    s->feat[px * 4 + 2] = sw;
+    s->feat[px * 4 + 3] = qw;
   }
   s->n_train = n;
   s->frame = n;
@@ -461,6 +476,148 @@ int orc_gmm_step(orc_state *s, const void *frame, uint8_t *mask) {
     for (int c = 0; c < C; ++c) s->prev[px * C + c] = x[c];
   }
   s->frame++;
+  return 0;
+}
+
+/* ---- spatio-temporal grouping (§2 "Clustering Similar Background"):
+ * steps 1-3 give per pixel the temporal variance of the dominant mode's
+ * adapted variance and weight over the training warm-up (the diagonal of
+ * the paper's Cov(V), Cov(R)); step 4 is K-means with K = 3; step 5 / eq. 3
+ * keeps a pixel in its cluster when its features lie within one standard
+ * deviation of the cluster's mean. -------------------------------------- */
+static uint32_t var_key(float S, float Q, float n) {
+  const float m = S / n;
+  float var = Q / n - m * m;
+  if (!(var > 0.0f)) var = 0.0f;
+  uint32_t u;
+  memcpy(&u, &var, 4);
+  return u >> 16;
+}
+
+int orc_group_keys(const orc_state *s, uint32_t *keys) {
+  if (!s || !keys || s->n_train < 2) return -1;
+  const float n = (float)(s->n_train - 1);
+  for (int64_t px = 0; px < s->npix; ++px) {
+    const float *f = s->feat + px * 4;
+    keys[px * 2 + 0] = var_key(f[0], f[1], n);
+    keys[px * 2 + 1] = var_key(f[2], f[3], n);
+  }
+  return 0;
+}
+
+static int64_t dist2(const uint32_t *k, const int64_t *c) {
+  const int64_t a = (int64_t)k[0] - c[0], b = (int64_t)k[1] - c[1];
+  return a * a + b * b;
+}
+
+int orc_group(const orc_state *s, uint8_t *map, double *info) {
+  if (!s || s->n_train < 2) return -1;
+  const int64_t P = s->npix;
+  const int G = ORC_NGROUPS;
+  uint32_t *keys = (uint32_t *)malloc((size_t)P * 2 * sizeof(uint32_t));
+  uint8_t *asg = (uint8_t *)malloc((size_t)P);
+  if (!keys || !asg) {
+    free(keys);
+    free(asg);
+    return -1;
+  }
+  orc_group_keys(s, keys);
+  /* initial centres: the minimum, the floor of the mean and the maximum of
+   * each key */
+  int64_t c[ORC_NGROUPS][2];
+  for (int d = 0; d < 2; ++d) {
+    uint32_t lo = keys[d], hi = keys[d];
+    uint64_t sum = 0;
+    for (int64_t px = 0; px < P; ++px) {
+      const uint32_t v = keys[px * 2 + d];
+      lo = v < lo ? v : lo;
+      hi = v > hi ? v : hi;
+      sum += v;
+    }
+    c[0][d] = lo;
+    c[1][d] = (int64_t)(sum / (uint64_t)P);
+    c[2][d] = hi;
+  }
+  /* Lloyd iterations: nearest centre (lowest index on ties), centres move
+   * to the floor of their members' mean; stop when no assignment changes */
+  int it = 0;
+  for (int64_t px = 0; px < P; ++px) asg[px] = 255;
+  for (it = 1; it <= ORC_GROUP_ITERS; ++it) {
+    int64_t changed = 0;
+    uint64_t cnt[ORC_NGROUPS] = {0}, sum[ORC_NGROUPS][2] = {{0}};
+    for (int64_t px = 0; px < P; ++px) {
+      int best = 0;
+      int64_t bd = dist2(keys + px * 2, c[0]);
+      for (int g = 1; g < G; ++g) {
+        const int64_t d = dist2(keys + px * 2, c[g]);
+        if (d < bd) {
+          bd = d;
+          best = g;
+        }
+      }
+      if (asg[px] != best) changed++;
+      asg[px] = (uint8_t)best;
+      cnt[best]++;
+      sum[best][0] += keys[px * 2];
+      sum[best][1] += keys[px * 2 + 1];
+    }
+    if (changed == 0) break;
+    for (int g = 0; g < G; ++g)
+      if (cnt[g])
+        for (int d = 0; d < 2; ++d) c[g][d] = (int64_t)(sum[g][d] / cnt[g]);
+  }
+  if (it > ORC_GROUP_ITERS) it = ORC_GROUP_ITERS;
+  /* eq. 3: one standard deviation around each cluster's member mean */
+  double mean[ORC_NGROUPS][2], sd[ORC_NGROUPS][2];
+  uint64_t cnt[ORC_NGROUPS] = {0};
+  uint64_t s1[ORC_NGROUPS][2] = {{0}}, s2[ORC_NGROUPS][2] = {{0}};
+  for (int64_t px = 0; px < P; ++px) {
+    const int g = asg[px];
+    cnt[g]++;
+    for (int d = 0; d < 2; ++d) {
+      const uint64_t v = keys[px * 2 + d];
+      s1[g][d] += v;
+      s2[g][d] += v * v;
+    }
+  }
+  for (int g = 0; g < G; ++g)
+    for (int d = 0; d < 2; ++d) {
+      if (!cnt[g]) {
+        mean[g][d] = sd[g][d] = 0.0;
+        continue;
+      }
+      const double n = (double)cnt[g];
+      mean[g][d] = (double)s1[g][d] / n;
+      double var = (double)s2[g][d] / n - mean[g][d] * mean[g][d];
+      sd[g][d] = var > 0.0 ? sqrt(var) : 0.0;
+    }
+  uint64_t grouped[ORC_NGROUPS] = {0};
+  for (int64_t px = 0; px < P; ++px) {
+    const int g = asg[px];
+    int in = 1;
+    for (int d = 0; d < 2; ++d) {
+      const double e = (double)keys[px * 2 + d] - mean[g][d];
+      if (!(fabs(e) <= sd[g][d])) in = 0;
+    }
+    if (in) grouped[g]++;
+    if (map) map[px] = in ? (uint8_t)g : 255;
+  }
+  if (info) {
+    info[0] = it;
+    for (int g = 0; g < G; ++g) {
+      double *o = info + 1 + 8 * g;
+      o[0] = (double)cnt[g];
+      o[1] = (double)c[g][0];
+      o[2] = (double)c[g][1];
+      o[3] = mean[g][0];
+      o[4] = sd[g][0];
+      o[5] = mean[g][1];
+      o[6] = sd[g][1];
+      o[7] = (double)grouped[g];
+    }
+  }
+  free(keys);
+  free(asg);
   return 0;
 }
 

@@ -69,6 +69,22 @@ int orc_pixel_gmmstep(const orc_params *p, float *comp, const float *x, float al
 /* Background-set size B of a sorted record. */
 int orc_pixel_bgset(const orc_params *p, const float *comp);
 
+/* Spatio-temporal grouping of the background (§2 "Clustering Similar
+ * Background - Spatio-Temporal Grouping"), after training.  Per pixel, the
+ * training warm-up gives the temporal variance of the dominant component's
+ * adapted variance and of its weight; each becomes an integer key (its
+ * binary32 pattern >> 16, a piecewise-linear log2 scale).  Integer k-means
+ * with ORC_NGROUPS clusters groups the keys; a pixel keeps its cluster if
+ * both keys lie within one standard deviation of the cluster's member mean
+ * (closed interval), else it is ungrouped (255).
+ *   keys: P x 2 u32 (may be NULL); map: P bytes (may be NULL);
+ *   info (may be NULL): ORC_GROUP_INFO doubles =
+ *     {iterations, then per cluster g: count, center1, center2, mean1, sd1,
+ *      mean2, sd2, grouped} */
+enum { ORC_NGROUPS = 3, ORC_GROUP_ITERS = 32, ORC_GROUP_INFO = 1 + 8 * 3 };
+int orc_group_keys(const orc_state *s, uint32_t *keys);
+int orc_group(const orc_state *s, uint8_t *map, double *info);
+
 size_t orc_canonical_bytes(const orc_params *p);
 int orc_export(const orc_state *s, void *dst, size_t bytes);
 

@@ -80,6 +80,8 @@ def lib():
         L.orc_pixel_gmmstep.argtypes = [P(OrcParams), P(ct.c_float), P(ct.c_float), ct.c_float,
                                         P(ct.c_int), P(ct.c_int)]
         L.orc_pixel_bgset.argtypes = [P(OrcParams), P(ct.c_float)]
+        L.orc_group_keys.argtypes = [ct.c_void_p, P(ct.c_uint32)]
+        L.orc_group.argtypes = [ct.c_void_p, P(ct.c_uint8), P(ct.c_double)]
         L.orc_canonical_bytes.argtypes = [P(OrcParams)]
         L.orc_canonical_bytes.restype = ct.c_size_t
         L.orc_export.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t]
@@ -183,6 +185,27 @@ class Oracle:
         if lib().orc_gmm_step(self._h, a.ctypes.data, mask.ctypes.data) != 0:
             raise RuntimeError("orc_gmm_step failed")
         return mask
+
+    def group_keys(self) -> np.ndarray:
+        """Per-pixel grouping keys [P, 2] (u32) from the training warm-up."""
+        out = np.zeros((self.npix, 2), dtype=np.uint32)
+        if lib().orc_group_keys(self._h, out.ctypes.data_as(ct.POINTER(ct.c_uint32))) != 0:
+            raise RuntimeError("orc_group_keys failed (train first)")
+        return out
+
+    def group(self):
+        """(map [P] u8 with 255 = ungrouped, info dict) of the spatio-temporal grouping."""
+        m = np.zeros(self.npix, dtype=np.uint8)
+        info = np.zeros(1 + 8 * 3, dtype=np.float64)
+        if lib().orc_group(self._h, m.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                           info.ctypes.data_as(ct.POINTER(ct.c_double))) != 0:
+            raise RuntimeError("orc_group failed (train first)")
+        groups = []
+        for g in range(3):
+            o = info[1 + 8 * g:9 + 8 * g]
+            groups.append(dict(count=int(o[0]), center=(int(o[1]), int(o[2])), mean=(o[3], o[5]),
+                               sd=(o[4], o[6]), grouped=int(o[7])))
+        return m, dict(iterations=int(info[0]), groups=groups)
 
     def export(self) -> bytes:
         nb = lib().orc_canonical_bytes(ct.byref(self.params))
