@@ -169,12 +169,41 @@ void cog_destroy(cog_ctx *h);
  * then sections each padded to 64 bytes: gmm f32[P][K][C+2] (w, mu[C], var in
  * rank order), rga f32[P][C+1] (mu_r[C], var_r), table u8[P][C][16],
  * cnt u16[P][3], label u8[P] (0/1), prev f32[P][C], sat u16[P] (sampling
- * counters; version 2 of the layout; version-1 states, without that section,
- * are still imported with zero counters).  For checkpoint/resume and tests;
+ * counters) and gkey u32[P][2] (grouping keys): version 2 of the layout;
+ * version-1 states, without the last two sections, are still imported with
+ * zero counters and keys.  For checkpoint/resume and tests;
  * synchronous; host buffers only. */
 cog_status cog_canonical_bytes(const cog_params *p, size_t *bytes);
 cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes);
 cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes);
+
+/* Spatio-temporal grouping of the background (§2 "Clustering Similar
+ * Background - Spatio-Temporal Grouping"), on a trained cascade context.
+ * Per pixel the training warm-up recorded the temporal variance of the
+ * dominant component's adapted variance and of its weight (the diagonal of
+ * the paper's Cov(V), Cov(R)), as integer keys (binary32 pattern >> 16).
+ * Integer k-means with 3 clusters (initial centres: min, mean, max of each
+ * key; nearest centre, lowest index on ties; centres at the floor of their
+ * members' mean; until no change, at most 32 passes) groups the pixels; a
+ * pixel stays in its cluster when both keys lie within one standard
+ * deviation of the cluster's member mean (eq. 3, closed interval).
+ * map_out (P bytes, device or host, may be NULL): cluster 0..2, 255 for an
+ * ungrouped pixel.  info may be NULL.  Synchronous; uses temporary device
+ * memory.  COG_E_STATE before training; COG_E_UNSUPPORTED on the baseline
+ * path. */
+typedef struct {
+  int64_t count;        /* pixels assigned to the cluster */
+  int64_t grouped;      /* of those, inside the one-sigma band */
+  int64_t center[2];    /* final centre (keys) */
+  double mean[2], sd[2];
+} cog_group_stats;
+typedef struct {
+  int32_t iterations;
+  int32_t reserved;
+  cog_group_stats group[3];
+} cog_group_info;
+cog_status cog_group_background(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,
+                                cog_group_info *info);
 
 /* Integer prior kernel weights W[b][v] (16 x 256, row-major) for bandwidth h,
  * as used by the training kernel; host-only, needs no GPU. */

@@ -623,7 +623,8 @@ int orc_group(const orc_state *s, uint8_t *map, double *info) {
 
 /* ---- canonical export: 64-byte header (version 2), then sections each
  * padded to 64 B: gmm f32[P][K][C+2], rga f32[P][C+1], table u8[P][C][16],
- * cnt u16[P][3], label u8[P], prev f32[P][C], sat u16[P]. ------------------ */
+ * cnt u16[P][3], label u8[P], prev f32[P][C], sat u16[P], gkey u32[P][2]
+ * (the grouping keys of the training warm-up). ----------------------------- */
 static size_t pad64(size_t n) { return (n + 63) & ~(size_t)63; }
 
 size_t orc_canonical_bytes(const orc_params *p) {
@@ -631,7 +632,7 @@ size_t orc_canonical_bytes(const orc_params *p) {
   const size_t P = (size_t)p->width * p->height;
   const size_t C = (size_t)p->channels, K = (size_t)p->K;
   return 64 + pad64(P * K * (C + 2) * 4) + pad64(P * (C + 1) * 4) + pad64(P * C * NBINS) +
-         pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2);
+         pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2) + pad64(P * 8);
 }
 
 int orc_export(const orc_state *s, void *dst, size_t bytes) {
@@ -662,5 +663,7 @@ int orc_export(const orc_state *s, void *dst, size_t bytes) {
   memcpy(o + off, s->prev, P * C * 4);
   off += pad64(P * C * 4);
   memcpy(o + off, s->sat, P * 2);
+  off += pad64(P * 2);
+  if (s->n_train >= 2) orc_group_keys(s, (uint32_t *)(o + off));
   return 0;
 }

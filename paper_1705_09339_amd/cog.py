@@ -91,6 +91,21 @@ class cog_server_stats(ct.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class cog_group_stats(ct.Structure):
+    _fields_ = [("count", ct.c_int64), ("grouped", ct.c_int64), ("center", ct.c_int64 * 2),
+                ("mean", ct.c_double * 2), ("sd", ct.c_double * 2)]
+
+
+class cog_group_info(ct.Structure):
+    _fields_ = [("iterations", ct.c_int32), ("reserved", ct.c_int32),
+                ("group", cog_group_stats * 3)]
+
+    def as_dict(self) -> dict:
+        return dict(iterations=self.iterations, groups=[
+            dict(count=g.count, center=(g.center[0], g.center[1]), mean=(g.mean[0], g.mean[1]),
+                 sd=(g.sd[0], g.sd[1]), grouped=g.grouped) for g in self.group])
+
+
 class CogError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -116,6 +131,7 @@ def _load(path: str = LIB_PATH):
         "cog_import_state": ([V, V, ct.c_size_t], ct.c_int),
         "cog_kde_weights": ([ct.c_float, P(ct.c_uint16)], ct.c_int),
         "cog_last_error": ([V], ct.c_char_p),
+        "cog_group_background": ([V, V, ct.c_int32, P(cog_group_info)], ct.c_int),
         "cog_batch_create": ([V, ct.c_int32, P(V)], ct.c_int),
         "cog_batch_tick": ([V, P(cog_tick_item), ct.c_int32], ct.c_int),
         "cog_batch_autotune": ([V, P(cog_tick_item), ct.c_int32, ct.c_int32, P(cog_schedule)], ct.c_int),
@@ -144,6 +160,7 @@ lib = _load()
 EXPORTED = ("cog_default_params", "cog_state_bytes", "cog_canonical_bytes", "cog_create",
             "cog_train_prior", "cog_step", "cog_step_frames", "cog_reset", "cog_destroy",
             "cog_export_state", "cog_import_state", "cog_kde_weights", "cog_last_error",
+            "cog_group_background",
             "cog_batch_create", "cog_batch_tick", "cog_batch_autotune", "cog_batch_set_schedule",
             "cog_batch_get_schedule", "cog_batch_destroy",
             "cog_server_create", "cog_server_open", "cog_server_submit", "cog_server_close",
@@ -268,6 +285,16 @@ def cog_kde_weights(hw: float = 8.0) -> np.ndarray:
     return out
 
 
+def cog_group_background(h: int, map_out=None) -> dict:
+    """Spatio-temporal grouping after training; fills map_out (P bytes, numpy
+    or torch, 255 = ungrouped) if given and returns the info as a dict."""
+    mp, mdev, keep = _ptr(map_out)
+    info = cog_group_info()
+    _check(lib.cog_group_background(h, mp, mdev, ct.byref(info)), h)
+    del keep
+    return info.as_dict()
+
+
 def cog_last_error(h: Optional[int] = None) -> str:
     m = lib.cog_last_error(h)
     return m.decode() if m else ""
@@ -291,6 +318,9 @@ class CogStream:
 
     def reset(self):
         cog_reset(self.h)
+
+    def group(self, map_out=None) -> dict:
+        return cog_group_background(self.h, map_out)
 
     def export_state(self) -> bytes:
         return cog_export_state(self.h, self.params)

@@ -136,6 +136,8 @@ Plan make_plan(const cog_params *p) {
   if (cascade) off += align256((size_t)pl.Ppad * 8);
   pl.off_sat = off;
   if (cascade) off += align256((size_t)pl.Ppad * 2);
+  pl.off_gkey = off;
+  if (cascade) off += align256((size_t)pl.Ppad * 8);
   pl.off_prev = off;
   off += align256((size_t)pl.Ppad * pl.C * pl.sin);
   pl.off_labels = off;
@@ -318,7 +320,7 @@ cog_status cog_canonical_bytes(const cog_params *p, size_t *bytes) {
   if (!bytes) return fail(nullptr, COG_E_INVALID, "bytes is NULL");
   const size_t P = (size_t)p->width * p->height, C = (size_t)p->channels, K = (size_t)p->K;
   *bytes = 64 + pad64(P * K * (C + 2) * 4) + pad64(P * (C + 1) * 4) + pad64(P * C * 16) +
-           pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2);
+           pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2) + pad64(P * 8);
   return COG_OK;
 }
 
@@ -373,6 +375,7 @@ cog_status cog_create(const cog_params *p, void *hip_stream, void *device_state,
   h->buf.labels = reinterpret_cast<unsigned long long *>(h->dstate + pl.off_labels);
   h->buf.kdew = reinterpret_cast<const uint16_t *>(h->dstate + pl.off_kdew);
   h->buf.sat = reinterpret_cast<uint16_t *>(h->dstate + pl.off_sat);
+  h->buf.gkey = reinterpret_cast<uint2 *>(h->dstate + pl.off_gkey);
   h->buf.P = pl.P;
 
   // prior kernel weights, uploaded level-major [256][16]
@@ -546,6 +549,8 @@ cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes) {
   }
   off += pad64(P * C * 4);
   if (aos) std::memcpy(o + off, raw.data() + pl.off_sat, P * 2);
+  off += pad64(P * 2);
+  if (aos) std::memcpy(o + off, raw.data() + pl.off_gkey, P * 8);
   return COG_OK;
 }
 
@@ -558,8 +563,8 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
   std::memcpy(&ver, in + 4, 4);
   size_t need = 0;
   cog_canonical_bytes(&h->p, &need);
-  // version 1 has no saturation section
-  if (ver == 1u) need -= pad64((size_t)h->plan.P * 2);
+  // version 1 has no saturation and grouping-key sections
+  if (ver == 1u) need -= pad64((size_t)h->plan.P * 2) + pad64((size_t)h->plan.P * 8);
   if (bytes < need) return fail(h, COG_E_INVALID, "buffer smaller than the canonical state");
   uint32_t h32[2];
   int32_t hi[6];
@@ -632,6 +637,8 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
   }
   off += pad64(P * C * 4);
   if (aos && ver >= 2u) std::memcpy(raw.data() + pl.off_sat, in + off, P * 2);
+  off += pad64(P * 2);
+  if (aos && ver >= 2u) std::memcpy(raw.data() + pl.off_gkey, in + off, P * 8);
   hipError_t e = hipMemcpyAsync(h->dstate, raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "state upload");
@@ -639,6 +646,121 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
   h->frame = frame;
   h->kp = make_kparams(&h->p, h->n_train);
   return COG_OK;
+}
+
+cog_status cog_group_background(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,
+                                cog_group_info *info) {
+  if (!h) return fail(nullptr, COG_E_INVALID, "context is NULL");
+  if (h->p.path != COG_PATH_CASCADE) return fail(h, COG_E_UNSUPPORTED, "grouping needs the cascade path");
+  if (h->n_train == 0) return fail(h, COG_E_STATE, "cog_train_prior has not run");
+  const int64_t P = h->plan.P;
+  const int nb = cog::group_blocks(P);
+  const size_t part_words = (size_t)nb * cog::kGroupStat;
+  uint8_t *asg = nullptr, *dmap = nullptr;
+  uint64_t *part = nullptr;
+  const uint2 *keys = h->buf.gkey;
+  hipStream_t st = h->stream;
+  cog_status rc = COG_OK;
+  std::vector<uint64_t> hp(part_words);
+  std::vector<uint8_t> hmap;
+  auto check = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess && rc == COG_OK) rc = hip_fail(h, e, what);
+    return rc == COG_OK;
+  };
+  auto fetch = [&](size_t words) {
+    return check(hipMemcpyAsync(hp.data(), part, words * 8, hipMemcpyDeviceToHost, st), "copy") &&
+           check(hipStreamSynchronize(st), "grouping");
+  };
+  if (hipMalloc((void **)&asg, (size_t)P * 2) != hipSuccess ||
+      hipMalloc((void **)&part, part_words * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    if (asg) (void)hipFree(asg);
+    return fail(h, COG_E_OOM, "grouping scratch allocation failed");
+  }
+  dmap = map_out && map_on_device ? map_out : asg + P;
+  cog::GroupCenters c{};
+  cog::GroupBands bands{};
+  int it = 0;
+  uint64_t cnt[cog::kGroups] = {0}, s1[cog::kGroups][2] = {{0}}, s2[cog::kGroups][2] = {{0}};
+  // initial centres: minimum, floor of the mean, maximum of each key
+  if (check(cog::launch_group_range(keys, P, part, st), "grouping launch") && fetch((size_t)nb * 6)) {
+    for (int d = 0; d < 2; ++d) {
+      uint64_t lo = ~0ull, hi = 0, sum = 0;
+      for (int b = 0; b < nb; ++b) {
+        lo = std::min(lo, hp[(size_t)b * 6 + 3 * d]);
+        hi = std::max(hi, hp[(size_t)b * 6 + 3 * d + 1]);
+        sum += hp[(size_t)b * 6 + 3 * d + 2];
+      }
+      c.c[0][d] = (int64_t)lo;
+      c.c[1][d] = (int64_t)(sum / (uint64_t)P);
+      c.c[2][d] = (int64_t)hi;
+    }
+  }
+  if (rc == COG_OK) check(hipMemsetAsync(asg, 255, (size_t)P, st), "grouping");
+  // Lloyd passes until no assignment changes
+  for (it = 1; rc == COG_OK && it <= 32; ++it) {
+    if (!check(cog::launch_group_assign(keys, P, c, asg, part, st), "grouping launch") ||
+        !fetch(part_words))
+      break;
+    uint64_t changed = 0;
+    for (int g = 0; g < cog::kGroups; ++g) cnt[g] = s1[g][0] = s1[g][1] = s2[g][0] = s2[g][1] = 0;
+    for (int b = 0; b < nb; ++b) {
+      const uint64_t *r = hp.data() + (size_t)b * cog::kGroupStat;
+      changed += r[0];
+      for (int g = 0; g < cog::kGroups; ++g) {
+        cnt[g] += r[1 + 5 * g];
+        s1[g][0] += r[2 + 5 * g];
+        s1[g][1] += r[3 + 5 * g];
+        s2[g][0] += r[4 + 5 * g];
+        s2[g][1] += r[5 + 5 * g];
+      }
+    }
+    if (changed == 0) break;
+    for (int g = 0; g < cog::kGroups; ++g)
+      if (cnt[g])
+        for (int d = 0; d < 2; ++d) c.c[g][d] = (int64_t)(s1[g][d] / cnt[g]);
+  }
+  if (it > 32) it = 32;
+  // eq. 3: one standard deviation around each cluster's member mean
+  for (int g = 0; g < cog::kGroups; ++g)
+    for (int d = 0; d < 2; ++d) {
+      if (!cnt[g]) {
+        bands.mean[g][d] = bands.sd[g][d] = 0.0;
+        continue;
+      }
+      const double n = (double)cnt[g];
+      bands.mean[g][d] = (double)s1[g][d] / n;
+      const double var = (double)s2[g][d] / n - bands.mean[g][d] * bands.mean[g][d];
+      bands.sd[g][d] = var > 0.0 ? std::sqrt(var) : 0.0;
+    }
+  if (rc == COG_OK) check(cog::launch_group_map(keys, P, asg, bands, dmap, st), "grouping launch");
+  if (rc == COG_OK && (info || (map_out && !map_on_device))) {
+    hmap.resize((size_t)P);
+    check(hipMemcpyAsync(hmap.data(), dmap, (size_t)P, hipMemcpyDeviceToHost, st), "copy");
+  }
+  if (rc == COG_OK) check(hipStreamSynchronize(st), "grouping");
+  if (rc == COG_OK && map_out && !map_on_device) std::memcpy(map_out, hmap.data(), (size_t)P);
+  if (rc == COG_OK && info) {
+    std::memset(info, 0, sizeof(*info));
+    info->iterations = it;
+    int64_t grouped[cog::kGroups] = {0, 0, 0};
+    for (int64_t i = 0; i < P; ++i)
+      if (hmap[(size_t)i] < cog::kGroups) grouped[hmap[(size_t)i]]++;
+    for (int g = 0; g < cog::kGroups; ++g) {
+      cog_group_stats &o = info->group[g];
+      o.count = (int64_t)cnt[g];
+      o.grouped = grouped[g];
+      for (int d = 0; d < 2; ++d) {
+        o.center[d] = c.c[g][d];
+        o.mean[d] = bands.mean[g][d];
+        o.sd[d] = bands.sd[g][d];
+      }
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(asg);
+  (void)hipFree(part);
+  return rc;
 }
 
 const char *cog_last_error(const cog_ctx *h) {

@@ -19,8 +19,8 @@ struct Plan {
   int64_t P = 0, Ppad = 0;
   int C = 0, K = 0, R = 0, RG = 0, PB = 0, sin = 1;
   int tile = 0, ppt = 1, ntiles = 0, nslots = 0, nblk = 0;
-  size_t off_gmm = 0, off_rga = 0, off_prior = 0, off_cnt = 0, off_sat = 0, off_prev = 0,
-         off_labels = 0, off_kdew = 0, off_partials = 0, off_statout = 0, total = 0;
+  size_t off_gmm = 0, off_rga = 0, off_prior = 0, off_cnt = 0, off_sat = 0, off_gkey = 0,
+         off_prev = 0, off_labels = 0, off_kdew = 0, off_partials = 0, off_statout = 0, total = 0;
 };
 
 cog_status fail(cog_ctx *h, cog_status s, const std::string &msg);

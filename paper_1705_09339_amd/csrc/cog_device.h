@@ -42,6 +42,7 @@ struct Buffers {
   unsigned long long *labels;  // 1 bit per pixel, bit p&63 of word p>>6
   const uint16_t *kdew;        // prior kernel weights, level-major [256][16]
   uint16_t *sat;               // sampling: consecutive confident frames per pixel
+  uint2 *gkey;                 // grouping keys of the training warm-up, per pixel
   int64_t P;
 };
 
@@ -89,6 +90,18 @@ struct StatJob {
 };
 constexpr int kStatBlock = 4096;
 
+// ---- spatio-temporal grouping --------------------------------------------------
+constexpr int kGroups = 3;
+// Per-block sums of one assignment pass: changed, then per group count,
+// key sums (2) and key square sums (2).
+constexpr int kGroupStat = 1 + kGroups * 5;
+struct GroupCenters {
+  int64_t c[kGroups][2];
+};
+struct GroupBands {
+  double mean[kGroups][2], sd[kGroups][2];
+};
+
 // Launchers (cog_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_train(int C, int K, bool f32in, bool prior, bool aos, const Buffers &b,
                         const void *frames, int64_t stride, int n, const KParams &kp,
@@ -107,6 +120,14 @@ hipError_t launch_tick(int C, int K, bool f32in, bool lp, bool samp, TickHead *h
 hipError_t launch_stats(const StatJob &job, hipStream_t s);
 hipError_t launch_stats_table(const StatJob *jobs, int n, int max_blocks, int max_frames,
                               hipStream_t s);
+// Grouping: per-block {min, max, sum} of both keys ([blocks][6] u64), one
+// assignment pass (asg in/out, [blocks][kGroupStat] u64), and the final map.
+int group_blocks(int64_t P);
+hipError_t launch_group_range(const uint2 *keys, int64_t P, uint64_t *part, hipStream_t s);
+hipError_t launch_group_assign(const uint2 *keys, int64_t P, const GroupCenters &c, uint8_t *asg,
+                               uint64_t *part, hipStream_t s);
+hipError_t launch_group_map(const uint2 *keys, int64_t P, const uint8_t *asg, const GroupBands &b,
+                            uint8_t *map, hipStream_t s);
 // Workgroups of the class's tick kernel one compute unit keeps resident
 // (0 if the query fails).
 int tick_blocks_per_cu(int C, int K, bool f32in, bool lp, bool samp);

@@ -494,6 +494,16 @@ __device__ __forceinline__ uint32_t round_ratio255(uint32_t a, uint32_t d) {
   return (uint32_t)q;
 }
 
+// Grouping key of a temporal variance (§2 "Clustering Similar Background"):
+// var = Q/n - (S/n)^2 from the warm-up sums, clamped at 0, as the top 16
+// bits of its binary32 pattern (a piecewise-linear log2 scale).
+__device__ __forceinline__ uint32_t var_key(float S, float Q, float n) {
+  const float m = S / n;
+  float var = Q / n - m * m;
+  var = var > 0.0f ? var : 0.0f;
+  return __float_as_uint(var) >> 16;
+}
+
 template <int C, int K, bool F32, bool PRIOR>
 __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, int64_t stride,
                                                int n, KParams kp) {
@@ -515,6 +525,9 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
 #pragma unroll
       for (int q = 0; q < kBins; ++q) acc[c][q] = 0u;
     uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
+    // grouping features: sums over the warm-up of the dominant component's
+    // adapted variance and weight and of their squares
+    float sv = 0.0f, qv = 0.0f, sw = 0.0f, qw = 0.0f;
     float x[C], xp[C], xn[C];
     Mix<C, K> m;
     load_px<C, F32>(frames, p, x);
@@ -551,6 +564,12 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
         int l, mp;
         mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
         lab = l != 0;
+        if constexpr (with_prior) {
+          sv = sv + m.var[0];
+          qv = qv + m.var[0] * m.var[0];
+          sw = sw + m.w[0];
+          qw = qw + m.w[0] * m.w[0];
+        }
       }
 #pragma unroll
       for (int c = 0; c < C; ++c) xp[c] = x[c];
@@ -590,6 +609,7 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
       for (int c = 0; c < C; ++c) rg[c] = m.mu[0][c];
       rg[C] = m.var[0];
       b.sat[p] = 0;  // no confident frame yet (sampling)
+      b.gkey[p] = make_uint2(var_key(sv, qv, kp.nm1), var_key(sw, qw, kp.nm1));
     }
     if constexpr (aos) rec_store<C, K>(b.gmm + p * rec_floats(C, K), m);
     else grp_store<C, K>(b.gmm, p, m);
@@ -1568,6 +1588,112 @@ __global__ __launch_bounds__(kNT) void k_stats_table(const StatJob *jobs) {
 }
 
 // ============================================================================
+// Spatio-temporal grouping (§2 "Clustering Similar Background"): integer
+// k-means over the two warm-up keys of every pixel, then the one-sigma band
+// of eq. 3.  One thread per pixel; per-block sums are exact integers, so
+// the result does not depend on the order of the reduction.
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += (uint64_t)__shfl_xor((long long)v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  uint64_t t = 0;
+#pragma unroll
+  for (int i = 0; i < kNW; ++i) t += red[i];
+  return t;
+}
+
+__global__ __launch_bounds__(kNT) void k_group_range(const uint2 *keys, int64_t P, uint64_t *part) {
+  __shared__ uint64_t red[kNW];
+  __shared__ uint32_t rlo[kNW], rhi[kNW];
+  const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const bool valid = p < P;
+  const uint2 k = valid ? keys[p] : make_uint2(0u, 0u);
+  uint64_t out[6];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const uint32_t v = d ? k.y : k.x;
+    // the wave's minimum and maximum by lane exchange, then the block's
+    uint32_t lo = valid ? v : 0xffffffffu, hi = valid ? v : 0u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint32_t l2 = (uint32_t)__shfl_xor((int)lo, o, 64), h2 = (uint32_t)__shfl_xor((int)hi, o, 64);
+      lo = l2 < lo ? l2 : lo;
+      hi = h2 > hi ? h2 : hi;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      rlo[threadIdx.x >> 6] = lo;
+      rhi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    uint32_t blo = 0xffffffffu, bhi = 0u;
+#pragma unroll
+    for (int i = 0; i < kNW; ++i) {
+      blo = rlo[i] < blo ? rlo[i] : blo;
+      bhi = rhi[i] > bhi ? rhi[i] : bhi;
+    }
+    out[3 * d] = blo;
+    out[3 * d + 1] = bhi;
+    out[3 * d + 2] = block_sum_u64(valid ? (uint64_t)v : 0ull, red);
+  }
+  if (threadIdx.x < 6) part[(int64_t)blockIdx.x * 6 + threadIdx.x] = out[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kNT) void k_group_assign(const uint2 *keys, int64_t P, GroupCenters c,
+                                                      uint8_t *asg, uint64_t *part) {
+  __shared__ uint64_t red[kNW];
+  const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const bool valid = p < P;
+  const uint2 k = valid ? keys[p] : make_uint2(0u, 0u);
+  int best = 0;
+  int64_t bd = 0;
+#pragma unroll
+  for (int g = 0; g < kGroups; ++g) {
+    const int64_t a = (int64_t)k.x - c.c[g][0], b = (int64_t)k.y - c.c[g][1];
+    const int64_t d = a * a + b * b;
+    if (g == 0 || d < bd) {  // lowest index on ties
+      bd = d;
+      best = g;
+    }
+  }
+  uint64_t changed = 0;
+  if (valid) {
+    changed = asg[p] != (uint8_t)best ? 1u : 0u;
+    asg[p] = (uint8_t)best;
+  }
+  uint64_t out[kGroupStat];
+  out[0] = block_sum_u64(changed, red);
+#pragma unroll
+  for (int g = 0; g < kGroups; ++g) {
+    const bool in = valid && best == g;
+    out[1 + 5 * g] = block_sum_u64(in ? 1ull : 0ull, red);
+    out[2 + 5 * g] = block_sum_u64(in ? (uint64_t)k.x : 0ull, red);
+    out[3 + 5 * g] = block_sum_u64(in ? (uint64_t)k.y : 0ull, red);
+    out[4 + 5 * g] = block_sum_u64(in ? (uint64_t)k.x * k.x : 0ull, red);
+    out[5 + 5 * g] = block_sum_u64(in ? (uint64_t)k.y * k.y : 0ull, red);
+  }
+  if (threadIdx.x < kGroupStat) part[(int64_t)blockIdx.x * kGroupStat + threadIdx.x] = out[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kNT) void k_group_map(const uint2 *keys, int64_t P, const uint8_t *asg,
+                                                   GroupBands bands, uint8_t *map) {
+  const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (p >= P) return;
+  const uint2 k = keys[p];
+  const int g = asg[p];
+  bool in = true;
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const double e = (double)(d ? k.y : k.x) - bands.mean[g][d];
+    in = in && (fabs(e) <= bands.sd[g][d]);
+  }
+  map[p] = in ? (uint8_t)g : (uint8_t)255;
+}
+
+// ============================================================================
 // Plain Stauffer-Grimson baseline: every pixel runs the mixture step every
 // frame (alpha fixed), one wave per 64 pixels and one pixel per lane, the
 // mixture in registers across the frames of the launch, 64-pixel field-major
@@ -1751,6 +1877,27 @@ int tick_blocks_per_cu(int C, int K, bool f32in, bool lp, bool samp) {
 #undef COG_OCC_LP
 #undef COG_OCC
   return e == hipSuccess ? nb : 0;
+}
+
+int group_blocks(int64_t P) { return (int)((P + kNT - 1) / kNT); }
+
+hipError_t launch_group_range(const uint2 *keys, int64_t P, uint64_t *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_range, dim3((unsigned)group_blocks(P)), dim3(kNT), 0, s, keys, P, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_assign(const uint2 *keys, int64_t P, const GroupCenters &c, uint8_t *asg,
+                               uint64_t *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_assign, dim3((unsigned)group_blocks(P)), dim3(kNT), 0, s, keys, P, c,
+                     asg, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_map(const uint2 *keys, int64_t P, const uint8_t *asg, const GroupBands &b,
+                            uint8_t *map, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_map, dim3((unsigned)group_blocks(P)), dim3(kNT), 0, s, keys, P, asg, b,
+                     map);
+  return hipGetLastError();
 }
 
 hipError_t launch_stats(const StatJob &job, hipStream_t s) {

@@ -4,7 +4,8 @@ Layout: a 64-byte header {u32 magic 'COG1', u32 version, i32 width, height,
 channels, K, dtype, n_train, i64 frame}, then sections each padded to 64 bytes:
 gmm f32[P][K][C+2] (w, mu[C], var in rank order), rga f32[P][C+1],
 table u8[P][C][16], cnt u16[P][3], label u8[P], prev f32[P][C], and from
-version 2 on sat u16[P] (the sampling saturation counters).
+version 2 on sat u16[P] (the sampling saturation counters) and gkey u32[P][2]
+(the grouping keys of the training warm-up).
 """
 import numpy as np
 
@@ -37,6 +38,7 @@ def parse(blob: bytes) -> dict:
     ]
     if version >= 2:
         sections.append(("sat", np.uint16, (P,)))
+        sections.append(("gkey", np.uint32, (P, 2)))
     for name, dt, shape in sections:
         nbytes = int(np.prod(shape)) * np.dtype(dt).itemsize
         out[name] = b[off:off + nbytes].copy().view(dt).reshape(shape)

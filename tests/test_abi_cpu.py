@@ -51,7 +51,8 @@ def test_struct_layouts_match_header(C, tmp_path):
         lines.append(f'printf("%zu\\n", offsetof(cog_params, {cfields[f]}));')
     for f, _ in C.cog_step_info._fields_:
         lines.append(f'printf("%zu\\n", offsetof(cog_step_info, {f}));')
-    for st in (C.cog_tick_item, C.cog_schedule, C.cog_completion, C.cog_server_stats):
+    for st in (C.cog_tick_item, C.cog_schedule, C.cog_completion, C.cog_server_stats,
+               C.cog_group_stats, C.cog_group_info):
         lines.append(f'printf("%zu\\n", sizeof({st.__name__}));')
         for f, _ in st._fields_:
             lines.append(f'printf("%zu\\n", offsetof({st.__name__}, {f}));')
@@ -66,7 +67,8 @@ def test_struct_layouts_match_header(C, tmp_path):
     offs = vals[2:]
     exp = [getattr(C.cog_params, f).offset for f in fields_p] + \
           [getattr(C.cog_step_info, f).offset for f, _ in C.cog_step_info._fields_]
-    for st in (C.cog_tick_item, C.cog_schedule, C.cog_completion, C.cog_server_stats):
+    for st in (C.cog_tick_item, C.cog_schedule, C.cog_completion, C.cog_server_stats,
+               C.cog_group_stats, C.cog_group_info):
         exp += [ct.sizeof(st)] + [getattr(st, f).offset for f, _ in st._fields_]
     assert offs == exp
 
@@ -141,6 +143,7 @@ def test_null_context_calls_are_invalid(C):
     assert C.lib.cog_reset(None) == C.COG_E_INVALID
     assert C.lib.cog_step(None, None, 0, None, 0, None) == C.COG_E_INVALID
     assert C.lib.cog_train_prior(None, None, 10, 0) == C.COG_E_INVALID
+    assert C.lib.cog_group_background(None, None, 0, None) == C.COG_E_INVALID
     C.lib.cog_destroy(None)
 
 
