@@ -268,6 +268,20 @@ def main():
         log(f"latency p50 {lat['p50_ms']} ms p99 {lat['p99_ms']} ms; per-frame stream "
             f"{lat['per_frame_mpx_s']} Mpx/s")
 
+    # spatio-temporal grouping of the trained stream (one call, synchronous)
+    cog_ctx.reset()
+    cog_ctx.train_prior(dev[:N])
+    gmap = torch.empty(P, dtype=torch.uint8, device="cuda")
+    cog_ctx.group(gmap)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ginfo = cog_ctx.group(gmap)
+    g_ms = (time.perf_counter() - ts) * 1e3
+    grouping = {"ms": round(g_ms, 3), "iterations": ginfo["iterations"],
+                "grouped_frac": round(sum(g["grouped"] for g in ginfo["groups"]) / P, 4),
+                "cluster_sizes": [g["count"] for g in ginfo["groups"]]}
+    log(f"grouping: {grouping}")
+
     cog_ctx.close()
     gmm_ctx.close()
 
@@ -316,6 +330,7 @@ def main():
         "latency": lat,
         "roofline": roof,
         "sampling": samp,
+        "grouping": grouping,
         "accuracy_vs_ground_truth": acc,
     }
 

@@ -343,7 +343,7 @@ __device__ __forceinline__ void u8win_extract(uint32_t raw, const uint8_t *frame
 // frames are requested into registers and the ones requested a block
 // earlier are copied into an LDS ring, so a frame's input is an LDS read and
 // the global-memory wait is paid once per NB frames, on loads issued NB
-// frames before.  Frames past the end re-read the last frame (in bounds).
+// frames before.  Slots past the last frame are not loaded (and never read).
 template <int C, bool F32, int NB>
 struct InStage {
   static constexpr int NDW = F32 ? C : 1;
@@ -353,7 +353,8 @@ struct InStage {
                                         int64_t tile0, int npx, int lane) {
 #pragma unroll
     for (int kk = 0; kk < NB; ++kk) {
-      const int ff = fb + kk < nframes ? fb + kk : nframes - 1;
+      const int ff = fb + kk;
+      if (ff >= nframes) break;  // wave-uniform
       const void *xf = frame_ptr<C, F32>(x, stride, ff);
       if constexpr (F32) {
         const uint32_t *base = reinterpret_cast<const uint32_t *>(xf) + tile0 * C;
