@@ -259,8 +259,9 @@ cog_status cog_batch_create(void *hip_stream, int32_t max_items, cog_batch **out
  * tiles other than 64 pixels), COG_E_DEVICE. */
 cog_status cog_batch_tick(cog_batch *b, const cog_tick_item *items, int32_t n);
 
-/* Time candidate schedules on this tick's work (reps ticks each) and keep
- * the fastest per class.  Every context's state is restored after each
+/* Time candidate schedules on this tick's work (reps ticks each, median)
+ * and keep, per class, the current schedule unless a candidate is more than
+ * 3 % faster (then the fastest).  Every context's state is restored after each
  * trial, so the streams are left as they were; the masks of the items are
  * written (with the tick's result) and no infos are filled.  best (may be
  * NULL) receives the schedule kept for the first item's class.  Needs

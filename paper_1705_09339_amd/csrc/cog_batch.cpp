@@ -494,7 +494,12 @@ cog_status cog_batch_autotune(cog_batch *b, const cog_tick_item *items, int32_t 
     cog_schedule best_s = default_schedule();
     auto it0 = b->sched.find(key);
     if (it0 != b->sched.end()) best_s = it0->second;
-    for (cog_schedule c : cand) {
+    // the incumbent is timed first; a candidate replaces it only when it is
+    // faster by more than the tick-to-tick noise (3 %)
+    std::vector<cog_schedule> trial{best_s};
+    trial.insert(trial.end(), cand.begin(), cand.end());
+    bool first = true;
+    for (cog_schedule c : trial) {
       if (c.blocks_per_cu == -2) c.blocks_per_cu = std::min(64, 2 * occ_lim);
       b->sched[key] = c;
       std::vector<float> t;
@@ -519,10 +524,11 @@ cog_status cog_batch_autotune(cog_batch *b, const cog_tick_item *items, int32_t 
       if (s != COG_OK) break;
       std::sort(t.begin(), t.end());
       const float med = t[t.size() / 2];
-      if (med < best_ms) {
+      if (first || med < 0.97f * best_ms) {
         best_ms = med;
         best_s = c;
       }
+      first = false;
     }
     b->sched[key] = best_s;
     if (j == 0 && best) *best = best_s;
