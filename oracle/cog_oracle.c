@@ -512,16 +512,19 @@ static int64_t dist2(const uint32_t *k, const int64_t *c) {
 
 int orc_group(const orc_state *s, uint8_t *map, double *info) {
   if (!s || s->n_train < 2) return -1;
-  const int64_t P = s->npix;
-  const int G = ORC_NGROUPS;
-  uint32_t *keys = (uint32_t *)malloc((size_t)P * 2 * sizeof(uint32_t));
-  uint8_t *asg = (uint8_t *)malloc((size_t)P);
-  if (!keys || !asg) {
-    free(keys);
-    free(asg);
-    return -1;
-  }
+  uint32_t *keys = (uint32_t *)malloc((size_t)s->npix * 2 * sizeof(uint32_t));
+  if (!keys) return -1;
   orc_group_keys(s, keys);
+  const int rc = orc_group_run(keys, s->npix, map, info);
+  free(keys);
+  return rc;
+}
+
+int orc_group_run(const uint32_t *keys, int64_t P, uint8_t *map, double *info) {
+  if (!keys || P < 1) return -1;
+  const int G = ORC_NGROUPS;
+  uint8_t *asg = (uint8_t *)malloc((size_t)P);
+  if (!asg) return -1;
   /* initial centres: the minimum, the floor of the mean and the maximum of
    * each key */
   int64_t c[ORC_NGROUPS][2];
@@ -616,7 +619,6 @@ int orc_group(const orc_state *s, uint8_t *map, double *info) {
       o[7] = (double)grouped[g];
     }
   }
-  free(keys);
   free(asg);
   return 0;
 }

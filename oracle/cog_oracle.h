@@ -84,6 +84,8 @@ int orc_pixel_bgset(const orc_params *p, const float *comp);
 enum { ORC_NGROUPS = 3, ORC_GROUP_ITERS = 32, ORC_GROUP_INFO = 1 + 8 * 3 };
 int orc_group_keys(const orc_state *s, uint32_t *keys);
 int orc_group(const orc_state *s, uint8_t *map, double *info);
+/* The clustering and eq. 3 band alone, on given keys (P x 2 u32, P >= 1). */
+int orc_group_run(const uint32_t *keys, int64_t P, uint8_t *map, double *info);
 
 size_t orc_canonical_bytes(const orc_params *p);
 int orc_export(const orc_state *s, void *dst, size_t bytes);

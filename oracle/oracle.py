@@ -82,6 +82,7 @@ def lib():
         L.orc_pixel_bgset.argtypes = [P(OrcParams), P(ct.c_float)]
         L.orc_group_keys.argtypes = [ct.c_void_p, P(ct.c_uint32)]
         L.orc_group.argtypes = [ct.c_void_p, P(ct.c_uint8), P(ct.c_double)]
+        L.orc_group_run.argtypes = [P(ct.c_uint32), ct.c_int64, P(ct.c_uint8), P(ct.c_double)]
         L.orc_canonical_bytes.argtypes = [P(OrcParams)]
         L.orc_canonical_bytes.restype = ct.c_size_t
         L.orc_export.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t]
@@ -127,6 +128,27 @@ def pixel_gmmstep(params: OrcParams, comp: np.ndarray, x, alpha_e: float):
                             xv.ctypes.data_as(ct.POINTER(ct.c_float)), float(alpha_e),
                             ct.byref(lab), ct.byref(mp))
     return comp, lab.value, mp.value
+
+
+def _group_info(info) -> dict:
+    groups = []
+    for g in range(3):
+        o = info[1 + 8 * g:9 + 8 * g]
+        groups.append(dict(count=int(o[0]), center=(int(o[1]), int(o[2])), mean=(o[3], o[5]),
+                           sd=(o[4], o[6]), grouped=int(o[7])))
+    return dict(iterations=int(info[0]), groups=groups)
+
+
+def group_run(keys) -> tuple:
+    """The grouping's clustering and band on given keys [P, 2] (u32)."""
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    m = np.zeros(len(k), dtype=np.uint8)
+    info = np.zeros(1 + 8 * 3, dtype=np.float64)
+    if lib().orc_group_run(k.ctypes.data_as(ct.POINTER(ct.c_uint32)), len(k),
+                           m.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                           info.ctypes.data_as(ct.POINTER(ct.c_double))) != 0:
+        raise ValueError("orc_group_run failed")
+    return m, _group_info(info)
 
 
 def pixel_bgset(params: OrcParams, comp: np.ndarray) -> int:
@@ -200,12 +222,7 @@ class Oracle:
         if lib().orc_group(self._h, m.ctypes.data_as(ct.POINTER(ct.c_uint8)),
                            info.ctypes.data_as(ct.POINTER(ct.c_double))) != 0:
             raise RuntimeError("orc_group failed (train first)")
-        groups = []
-        for g in range(3):
-            o = info[1 + 8 * g:9 + 8 * g]
-            groups.append(dict(count=int(o[0]), center=(int(o[1]), int(o[2])), mean=(o[3], o[5]),
-                               sd=(o[4], o[6]), grouped=int(o[7])))
-        return m, dict(iterations=int(info[0]), groups=groups)
+        return m, _group_info(info)
 
     def export(self) -> bytes:
         nb = lib().orc_canonical_bytes(ct.byref(self.params))

@@ -109,3 +109,32 @@ def test_grouping_is_pixel_permutation_invariant():
     mb, ib = b.group()
     assert np.array_equal(ma[perm], mb)
     assert ia == ib
+
+
+# ---- the clustering on hand-made keys ----------------------------------------------
+
+def test_kmeans_initial_centres_and_ties():
+    """Two pixels with keys (0,0) and (1,0): the centres start at the minimum
+    (0,0), the floor of the mean (0,0) and the maximum (1,0); pixel 0 is
+    equally near centres 0 and 1 and takes 0 (lowest index); pixel 1 takes 2."""
+    m, info = O.group_run([[0, 0], [1, 0]])
+    assert [g["count"] for g in info["groups"]] == [1, 0, 1]
+    assert info["groups"][0]["center"] == (0, 0) and info["groups"][2]["center"] == (1, 0)
+    assert list(m) == [0, 2] and info["iterations"] == 2
+
+
+def test_kmeans_three_obvious_clusters():
+    """Three separated clouds placed at the minimum, the mean and the maximum
+    of the keys end in three clusters whose centres are the floors of the
+    cloud means; eq. 3's closed one-sigma band keeps a and b whole and only
+    the centre point of c (hand-checked: c's standard deviation is 0.894)."""
+    a = [[0, 0], [2, 0], [0, 2], [2, 2]]                      # mean (1, 1), sd (1, 1)
+    b = [[500, 500], [502, 500]]                              # mean (501, 500), sd (1, 0)
+    c = [[1000, 1000], [1002, 1000], [1000, 1002], [1002, 1002], [1001, 1001]]
+    m, info = O.group_run(a + b + c)
+    g = info["groups"]
+    assert info["iterations"] == 2
+    assert [x["count"] for x in g] == [4, 2, 5]
+    assert [x["center"] for x in g] == [(1, 1), (501, 500), (1001, 1001)]
+    assert list(m) == [0, 0, 0, 0, 1, 1, 255, 255, 255, 255, 2]
+    assert [x["grouped"] for x in g] == [4, 2, 1]

@@ -112,11 +112,12 @@ def test_period_one_is_sampling_off():
     assert (sa["sat"] == 0).all() and (sb["sat"] > 0).any()
 
 
-def test_one_unconfident_pixel_resets_its_block():
+@pytest.mark.parametrize("row,col", [(0, 5), (1, 31)])  # inside block 0, and its last pixel
+def test_one_unconfident_pixel_resets_its_block(row, col):
     N, W_frames, period = 6, 3, 2
     w, h = 32, 4  # two blocks of 64
     fr = synth.constant_stream(N + 40, h, w, 3, [80, 80, 80])
-    fr[N + 12, 0, 5] = [250, 10, 250]  # block 0, pixel 5: far outside every model
+    fr[N + 12, row, col] = [250, 10, 250]  # far outside every model
     o = O.Oracle(_params(w, h, stage_mask=7 | SAMPLE, samp_window=W_frames, samp_period=period))
     o.train(fr[:N])
     skips = []
@@ -138,7 +139,7 @@ def test_one_unconfident_pixel_resets_its_block():
     assert st["sat"][64:].min() >= W_frames
 
 
-@pytest.mark.parametrize("delta,confident", [(10, True), (20, False)])
+@pytest.mark.parametrize("delta,confident", [(10, True), (16, True), (18, False), (20, False)])
 def test_confidence_gate_at_07_sigma(delta, confident):
     """After training on a constant, sigma_r^2 has the closed form
     max(var_min, var_init (1-alpha)^(N-1)); a step of delta in one channel is
