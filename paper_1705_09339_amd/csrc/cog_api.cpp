@@ -195,6 +195,9 @@ cog::KParams make_kparams(const cog_params *p, int32_t n_train) {
   k.samp_window = (uint32_t)(p->samp_window > 0 ? p->samp_window : 1);
   k.samp_period = (uint32_t)(p->samp_period > 0 ? p->samp_period : 1);
   k.lam_s2 = p->samp_lambda * p->samp_lambda;
+  // the cascade divides integer frame differences by res_e2 through this
+  // reciprocal (exact in that range; outside it, it divides)
+  k.inv_res_e2 = (p->res_e2 >= 0x1p-20f && p->res_e2 <= 0x1p20f) ? 1.0f / p->res_e2 : 0.0f;
   return k;
 }
 

@@ -30,6 +30,7 @@ struct KParams {
   uint32_t stage_mask;
   uint32_t samp_window, samp_period;  // sampling: saturation window, evaluation period
   float lam_s2;                       // sampling: confidence gate squared
+  float inv_res_e2;  // 1 / res_e2 correctly rounded when res_e2 is in [2^-20, 2^20], else 0
 };
 
 // Device state of one stream (see the host planner for sizes).

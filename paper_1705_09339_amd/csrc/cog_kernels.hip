@@ -15,6 +15,31 @@ namespace cog {
 namespace {
 
 // ----------------------------------------------------------------------------
+// a / d correctly rounded from y = 1/d correctly rounded: q = a y, then twice
+// q <- q + (a - d q) y with the residual formed by a fused multiply-add.  The
+// first correction leaves q within one unit in the last place of a / d, so
+// its residual is exact, and the second returns the correctly rounded
+// quotient (Markstein's theorem).  It holds when |d| is in [2^-20, 2^20] and
+// a is +0 or |a| is in [2^-100, 2^60]: then no residual loses bits to
+// underflow and nothing overflows.  Callers check that range (or know it) and
+// divide outside it; one reciprocal then serves every quotient by d.
+__device__ __forceinline__ float quot_recip(float a, float d, float y) {
+  const float q0 = a * y;
+  const float q1 = __builtin_fmaf(__builtin_fmaf(-d, q0, a), y, q0);
+  return __builtin_fmaf(__builtin_fmaf(-d, q1, a), y, q1);
+}
+
+// Bit patterns of the range bounds above (binary32, positive).
+constexpr uint32_t kDivisorLo = 0x35800000u;  // 2^-20
+constexpr uint32_t kDivisorHi = 0x49800000u;  // 2^20
+constexpr uint32_t kDividendLo = 0x0d800000u; // 2^-100
+constexpr uint32_t kDividendHi = 0x5d800000u; // 2^60
+
+__device__ __forceinline__ bool divisor_in_range(float d) {
+  return __float_as_uint(d) - kDivisorLo <= kDivisorHi - kDivisorLo;  // positive d only
+}
+
+// ----------------------------------------------------------------------------
 // Per-pixel Stauffer-Grimson mixture held in registers.
 template <int C, int K>
 struct Mix {
@@ -34,19 +59,18 @@ __device__ __forceinline__ void mix_init(Mix<C, K> &s, const float (&x)[C], floa
   }
 }
 
-// Background set B: the smallest b whose cumulative weight exceeds T.
+// Background set B: the smallest b whose cumulative weight exceeds T (K when
+// none does).  Written as a running minimum over the candidates b + 1, which
+// increase with b, so it compiles to selects rather than branches.
 template <int C, int K>
 __device__ __forceinline__ int mix_bgset(const Mix<C, K> &s, float T) {
   float cum = 0.0f;
   int B = K;
-  bool closed = false;
 #pragma unroll
   for (int b = 0; b < K; ++b) {
     cum = cum + s.w[b];
-    if (!closed && cum > T) {
-      B = b + 1;
-      closed = true;
-    }
+    const int cand = cum > T ? b + 1 : K;
+    B = cand < B ? cand : B;
   }
   return B;
 }
@@ -61,17 +85,19 @@ template <int C, int K>
 __device__ __forceinline__ void mix_step(Mix<C, K> &s, const float (&x)[C], float ae,
                                          const KParams &kp, int &label, int &mpost) {
   const int B = mix_bgset<C, K>(s, kp.T);
+  // first matching rank: every distance is evaluated (no short-circuit) and
+  // the scan runs from the last rank down, so the lowest hit wins as a select
   int m = -1;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = K - 1; k >= 0; --k) {
     float d2 = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const float d = x[c] - s.mu[k][c];
       d2 = d2 + d * d;
     }
-    const bool hit = (s.w[k] > 0.0f) && (d2 <= kp.lam2 * s.var[k]);
-    if (m < 0 && hit) m = k;
+    const bool hit = (s.w[k] > 0.0f) & (d2 <= kp.lam2 * s.var[k]);
+    m = hit ? k : m;
   }
   label = (m >= 0 && m < B) ? 0 : 1;
 
@@ -123,8 +149,24 @@ __device__ __forceinline__ void mix_step(Mix<C, K> &s, const float (&x)[C], floa
   float S = 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) S = S + s.w[k];
+  // the K quotients w_k / S share one reciprocal when S and every w_k are in
+  // quot_recip's range: the smallest (pattern - 1) skips zeros (+0 wraps to
+  // the top), the largest pattern rejects negatives, infinities and NaNs
+  uint32_t lo = 0xffffffffu, hi = 0u;
 #pragma unroll
-  for (int k = 0; k < K; ++k) s.w[k] = s.w[k] / S;
+  for (int k = 0; k < K; ++k) {
+    const uint32_t u = __float_as_uint(s.w[k]);
+    lo = min(lo, u - 1u);
+    hi = max(hi, u);
+  }
+  if (divisor_in_range(S) && lo >= kDividendLo - 1u && hi <= kDividendHi) {
+    const float y = 1.0f / S;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s.w[k] = quot_recip(s.w[k], S, y);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) s.w[k] = s.w[k] / S;
+  }
 
   // Re-rank by w/sigma: stable insertion sort.  If no adjacent pair is out of
   // order the insertion sort exchanges nothing (every pass stops at its first
@@ -461,13 +503,24 @@ __device__ __forceinline__ float confidence(const uint8_t *rec, const float (&x)
   uint32_t prod = 1u;
 #pragma unroll
   for (int c = 0; c < C; ++c) prod = prod * (uint32_t)rec[c * kBins + (quant<F32>(x[c], kp) >> 4)];
-  const float ph = (float)prod / (C == 3 ? 16581375.0f : 255.0f);
+  // prod is an integer in [0, 255^C] and the divisor a constant whose
+  // reciprocal is rounded at compile time: dividends of at least 1 and
+  // quotients in [2^-24, 1] keep quot_recip exact (all 255^C + 1 cases agree
+  // with the division, checked exhaustively)
+  constexpr float kTop = C == 3 ? 16581375.0f : 255.0f;
+  const float ph = quot_recip((float)prod, kTop, 1.0f / kTop);
   const float *abg = reinterpret_cast<const float *>(rec + C * kBins);
   float a = abg[0];
   const float bw = abg[1];
   const float g = abg[2];
   if (ph < kp.p_null) a = 0.0f;
-  float dh = 1.0f - dl / kp.res_e2;
+  // u8 input: dl is an integer in [0, 255], in range whenever res_e2 is
+  // (inv_res_e2 != 0, a uniform branch)
+  float dh;
+  if (!F32 && kp.inv_res_e2 != 0.0f)
+    dh = 1.0f - quot_recip(dl, kp.res_e2, kp.inv_res_e2);
+  else
+    dh = 1.0f - dl / kp.res_e2;
   dh = dh < 0.0f ? 0.0f : dh;
   float mh = 1.0f - dr2 / (kp.lam_m2 * var_r);
   mh = mh < 0.0f ? 0.0f : mh;
@@ -1335,7 +1388,9 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
         halted = ph != 0u && __ballot(sat < kp.samp_window) == 0ull;
         ph = ph + 1u == kp.samp_period ? 0u : ph + 1u;
       }
-      int st = -1;
+      // this frame's level, as lane flags read only by the statistics
+      // (S0, S1, S2 accepts, survivors of S2; halted lanes set none)
+      bool e0 = false, e1 = false, e2 = false, e3 = false;
       if (!halted) {
         float x[C];
         Stage::read_mis(s_in, k, mis, lane, x);
@@ -1377,7 +1432,8 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
         }
         dirty |= s1 ? 1u : 0u;
         lab = s1 ? 0u : lab;
-        st = !valid ? -1 : (s0 ? 0 : (s1 ? 1 : 3));
+        e0 = valid && s0;
+        e1 = valid && s1;
 
         if (valid && !s0 && !s1) {
           // survivor: first time in this launch, the mixture record is
@@ -1393,10 +1449,11 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
             accept = conf >= kp.conf_thr;
           }
           if (accept) {
-            st = 2;  // S2: background by the scene prior, nothing adapts
+            e2 = true;  // S2: background by the scene prior, nothing adapts
             lab = 0u;
           } else {
             // S3: the full mixture with the confidence-driven rate
+            e3 = true;
             const float ae = kp.alpha * (1.0f - kp.kappa * conf);
             int l, mp;
             mix_step<C, K>(m, x, ae, kp, l, mp);
@@ -1423,20 +1480,18 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) xp[c] = x[c];
-      } else {
-        st = valid ? 4 : -1;  // halted by sampling
       }
       // masks are streamed out: non-temporal (cache policy bit 1)
       __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(lab ? 255 : 0), mr, moff,
                                            k * (int)fr.mstride, 2);
       if (fr.partials) {
-        const uint32_t c0 = (uint32_t)__popcll(__ballot(st == 0));
-        const uint32_t c1 = (uint32_t)__popcll(__ballot(st == 1));
-        const uint32_t c2 = (uint32_t)__popcll(__ballot(st == 2));
-        const uint32_t c3 = (uint32_t)__popcll(__ballot(st == 3));
-        const uint32_t c3bg = (uint32_t)__popcll(__ballot(st == 3 && !lab));
+        const uint32_t c0 = (uint32_t)__popcll(__ballot(e0));
+        const uint32_t c1 = (uint32_t)__popcll(__ballot(e1));
+        const uint32_t c2 = (uint32_t)__popcll(__ballot(e2));
+        const uint32_t c3 = (uint32_t)__popcll(__ballot(e3));
+        const uint32_t c3bg = (uint32_t)__popcll(__ballot(e3 && !lab));
         const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
-        const uint32_t csk = SAMP ? (uint32_t)__popcll(__ballot(st == 4)) : 0u;
+        const uint32_t csk = SAMP ? (uint32_t)__popcll(__ballot(halted && valid)) : 0u;
         const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
                          : lane == 4 ? c3bg : lane == 5 ? cfg : lane == 6 ? csk : 0u;
         __builtin_amdgcn_raw_buffer_store_b32(v, sr, soff, k * srow, 0);
