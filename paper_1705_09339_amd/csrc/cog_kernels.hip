@@ -1380,121 +1380,136 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
         fr.partials ? nk * srow : 0, 0x00020000);
     int mis = (mis0 + f0 * mis_step) & 3;
 
-    for (int k = 0; k < nk; ++k, mis = (mis + mis_step) & 3) {
-      bool halted = false;
-      if constexpr (SAMP) {
-        // a block whose pixels are all saturated is evaluated only in phase;
-        // when halted the labels repeat, no level runs and nothing adapts
-        halted = ph != 0u && __ballot(sat < kp.samp_window) == 0ull;
-        ph = ph + 1u == kp.samp_period ? 0u : ph + 1u;
-      }
-      // this frame's level, as lane flags read only by the statistics
-      // (S0, S1, S2 accepts, survivors of S2; halted lanes set none)
-      bool e0 = false, e1 = false, e2 = false, e3 = false;
-      if (!halted) {
-        float x[C];
-        Stage::read_mis(s_in, k, mis, lane, x);
-
-        // S0 (frame difference) and S1 (running average) for every lane
-        float dl = 0.0f;
-#pragma unroll
-        for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xp[c]));
-        float dr2 = 0.0f;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const float d = x[c] - rmu[c];
-          dr2 = dr2 + d * d;
-        }
-        const bool s0 = fd_on && dl <= kp.tau_fd;
-        const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * rvar;
+    // one frame: reads the input into x; xq holds the previous frame's value.
+    // Frames alternate between two arrays, so no copy of x into the previous
+    // value is needed.
+    auto frame = [&](int k, int mis, float (&x)[C], const float (&xq)[C]) {
+        bool halted = false;
         if constexpr (SAMP) {
-          // confident: decided by the frame difference, or by the running
-          // average within samp_lambda standard deviations (its variance before
-          // this frame's update)
-          const bool conf = s0 || (s1 && dr2 <= kp.lam_s2 * rvar);
-          const uint32_t nsat = conf ? (sat < 65535u ? sat + 1u : 65535u) : 0u;
-          sat = valid ? nsat : sat;
+          // a block whose pixels are all saturated is evaluated only in phase;
+          // when halted the labels repeat, no level runs and nothing adapts
+          halted = ph != 0u && __ballot(sat < kp.samp_window) == 0ull;
+          ph = ph + 1u == kp.samp_period ? 0u : ph + 1u;
         }
-        {
-          float nmu[C];
-#pragma unroll
-          for (int c = 0; c < C; ++c) nmu[c] = kp.one_m_alpha_rga * rmu[c] + kp.alpha_rga * x[c];
-          float sr = 0.0f;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const float e = x[c] - nmu[c];
-            sr = sr + e * e;
-          }
-          const float nvar = fmaxf(kp.var_min, kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr);
-#pragma unroll
-          for (int c = 0; c < C; ++c) rmu[c] = s1 ? nmu[c] : rmu[c];
-          rvar = s1 ? nvar : rvar;
-        }
-        dirty |= s1 ? 1u : 0u;
-        lab = s1 ? 0u : lab;
-        e0 = valid && s0;
-        e1 = valid && s1;
+        // this frame's level, as lane flags read only by the statistics
+        // (S0, S1, S2 accepts, survivors of S2; halted lanes set none)
+        bool e0 = false, e1 = false, e2 = false, e3 = false;
+        if (!halted) {
+          Stage::read_mis(s_in, k, mis, lane, x);
 
-        if (valid && !s0 && !s1) {
-          // survivor: first time in this launch, the mixture record is
-          // requested before S2 runs
-          if (!have_rec) {
-            rec_load<C, K>(grec, m);
-            have_rec = 1u;
+          // S0 (frame difference) and S1 (running average) for every lane
+          float dl = 0.0f;
+  #pragma unroll
+          for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xq[c]));
+          float dr2 = 0.0f;
+  #pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const float d = x[c] - rmu[c];
+            dr2 = dr2 + d * d;
           }
-          float conf = 0.0f;
-          bool accept = false;
-          if (kde_on) {
-            conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
-            accept = conf >= kp.conf_thr;
+          const bool s0 = fd_on && dl <= kp.tau_fd;
+          const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * rvar;
+          if constexpr (SAMP) {
+            // confident: decided by the frame difference, or by the running
+            // average within samp_lambda standard deviations (its variance before
+            // this frame's update)
+            const bool conf = s0 || (s1 && dr2 <= kp.lam_s2 * rvar);
+            const uint32_t nsat = conf ? (sat < 65535u ? sat + 1u : 65535u) : 0u;
+            sat = valid ? nsat : sat;
           }
-          if (accept) {
-            e2 = true;  // S2: background by the scene prior, nothing adapts
-            lab = 0u;
-          } else {
-            // S3: the full mixture with the confidence-driven rate
-            e3 = true;
-            const float ae = kp.alpha * (1.0f - kp.kappa * conf);
-            int l, mp;
-            mix_step<C, K>(m, x, ae, kp, l, mp);
-            rec_dirty = 1u;
-            lab = l ? 1u : 0u;
-            if (!l) {
-              // background from the mixture: the running average takes the
-              // matched component (the transition update of the active level)
-              float sv = m.var[0];
-#pragma unroll
-              for (int c = 0; c < C; ++c) rmu[c] = m.mu[0][c];
-#pragma unroll
-              for (int kk = 1; kk < K; ++kk) {
-                if (mp == kk) {
-                  sv = m.var[kk];
-#pragma unroll
-                  for (int c = 0; c < C; ++c) rmu[c] = m.mu[kk][c];
+          {
+            float nmu[C];
+  #pragma unroll
+            for (int c = 0; c < C; ++c) nmu[c] = kp.one_m_alpha_rga * rmu[c] + kp.alpha_rga * x[c];
+            float sr = 0.0f;
+  #pragma unroll
+            for (int c = 0; c < C; ++c) {
+              const float e = x[c] - nmu[c];
+              sr = sr + e * e;
+            }
+            const float nvar = fmaxf(kp.var_min, kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr);
+  #pragma unroll
+            for (int c = 0; c < C; ++c) rmu[c] = s1 ? nmu[c] : rmu[c];
+            rvar = s1 ? nvar : rvar;
+          }
+          dirty |= s1 ? 1u : 0u;
+          lab = s1 ? 0u : lab;
+          e0 = valid && s0;
+          e1 = valid && s1;
+
+          if (valid && !s0 && !s1) {
+            // survivor: first time in this launch, the mixture record is
+            // requested before S2 runs
+            if (!have_rec) {
+              rec_load<C, K>(grec, m);
+              have_rec = 1u;
+            }
+            float conf = 0.0f;
+            bool accept = false;
+            if (kde_on) {
+              conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
+              accept = conf >= kp.conf_thr;
+            }
+            if (accept) {
+              e2 = true;  // S2: background by the scene prior, nothing adapts
+              lab = 0u;
+            } else {
+              // S3: the full mixture with the confidence-driven rate
+              e3 = true;
+              const float ae = kp.alpha * (1.0f - kp.kappa * conf);
+              int l, mp;
+              mix_step<C, K>(m, x, ae, kp, l, mp);
+              rec_dirty = 1u;
+              lab = l ? 1u : 0u;
+              if (!l) {
+                // background from the mixture: the running average takes the
+                // matched component (the transition update of the active level)
+                float sv = m.var[0];
+  #pragma unroll
+                for (int c = 0; c < C; ++c) rmu[c] = m.mu[0][c];
+  #pragma unroll
+                for (int kk = 1; kk < K; ++kk) {
+                  if (mp == kk) {
+                    sv = m.var[kk];
+  #pragma unroll
+                    for (int c = 0; c < C; ++c) rmu[c] = m.mu[kk][c];
+                  }
                 }
+                rvar = sv;
+                dirty = 1u;
               }
-              rvar = sv;
-              dirty = 1u;
             }
           }
+        } else {
+  #pragma unroll
+          for (int c = 0; c < C; ++c) x[c] = xq[c];
         }
+        // masks are streamed out: non-temporal (cache policy bit 1)
+        __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(lab ? 255 : 0), mr, moff,
+                                             k * (int)fr.mstride, 2);
+        if (fr.partials) {
+          const uint32_t c0 = (uint32_t)__popcll(__ballot(e0));
+          const uint32_t c1 = (uint32_t)__popcll(__ballot(e1));
+          const uint32_t c2 = (uint32_t)__popcll(__ballot(e2));
+          const uint32_t c3 = (uint32_t)__popcll(__ballot(e3));
+          const uint32_t c3bg = (uint32_t)__popcll(__ballot(e3 && !lab));
+          const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
+          const uint32_t csk = SAMP ? (uint32_t)__popcll(__ballot(halted && valid)) : 0u;
+          const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
+                           : lane == 4 ? c3bg : lane == 5 ? cfg : lane == 6 ? csk : 0u;
+          __builtin_amdgcn_raw_buffer_store_b32(v, sr, soff, k * srow, 0);
+        }
+    };
+    for (int k = 0; k < nk; k += 2) {
+      float xb[C];
+      frame(k, mis, xb, xp);
+      mis = (mis + mis_step) & 3;
+      if (k + 1 < nk) {
+        frame(k + 1, mis, xp, xb);
+        mis = (mis + mis_step) & 3;
+      } else {
 #pragma unroll
-        for (int c = 0; c < C; ++c) xp[c] = x[c];
-      }
-      // masks are streamed out: non-temporal (cache policy bit 1)
-      __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(lab ? 255 : 0), mr, moff,
-                                           k * (int)fr.mstride, 2);
-      if (fr.partials) {
-        const uint32_t c0 = (uint32_t)__popcll(__ballot(e0));
-        const uint32_t c1 = (uint32_t)__popcll(__ballot(e1));
-        const uint32_t c2 = (uint32_t)__popcll(__ballot(e2));
-        const uint32_t c3 = (uint32_t)__popcll(__ballot(e3));
-        const uint32_t c3bg = (uint32_t)__popcll(__ballot(e3 && !lab));
-        const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
-        const uint32_t csk = SAMP ? (uint32_t)__popcll(__ballot(halted && valid)) : 0u;
-        const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
-                         : lane == 4 ? c3bg : lane == 5 ? cfg : lane == 6 ? csk : 0u;
-        __builtin_amdgcn_raw_buffer_store_b32(v, sr, soff, k * srow, 0);
+        for (int c = 0; c < C; ++c) xp[c] = xb[c];
       }
     }
     wave_sync();
