@@ -25,6 +25,7 @@ namespace {
 
 constexpr int kMaxClasses = 8;     // classes in one tick
 constexpr int kMaxGraphs = 64;     // cached graph executables
+constexpr int kMaxSeen = 256;      // launch sets remembered for capture on reuse
 constexpr int kMaxItemsLimit = 4096;
 
 // A class of streams shares one kernel instantiation: channels, K, input
@@ -62,6 +63,17 @@ struct GraphEntry {
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
+// Workgroup counts rounded up to one of eight steps per octave (at most 1/8
+// of the workgroups find no unit and exit at once), so that ticks of varying
+// size share a few launch shapes and hence a few captured graphs.
+int64_t grid_bucket(int64_t n) {
+  if (n <= 16) return n;
+  int top = 63;
+  while (!((n >> top) & 1)) --top;
+  const int64_t q = (int64_t)1 << (top - 3);
+  return (n + q - 1) / q * q;
+}
+
 }  // namespace
 
 struct cog_batch {
@@ -82,6 +94,8 @@ struct cog_batch {
   std::map<ClassKey, cog_schedule> sched;
   std::map<std::tuple<int, int, int, int, int>, int> occ;
   std::vector<GraphEntry> graphs;
+  // launch sets seen once and not captured yet (most recent last)
+  std::vector<std::vector<int64_t>> seen;
   uint64_t use_clock = 0;
 };
 
@@ -188,12 +202,14 @@ cog_status plan_tick(cog_batch *b, const cog_tick_item *items, int32_t n, bool w
     L.graph = s.use_graph != 0;
     const int64_t units = (L.tiles + s.group - 1) / s.group;
     if (s.blocks_per_cu < 0) {
-      if (units > 0x7fffffff) return bfail(COG_E_INVALID, "tick too large for one workgroup per unit");
-      L.grid = (int)units;
+      const int64_t g = grid_bucket(units);
+      if (g > 0x7fffffff) return bfail(COG_E_INVALID, "tick too large for one workgroup per unit");
+      L.grid = (int)g;
       L.dynamic = 0;
     } else {
       const int bpc = s.blocks_per_cu == 0 ? occupancy(b, L.key, L.lp) : s.blocks_per_cu;
-      L.grid = (int)std::min<int64_t>(units, (int64_t)bpc * b->ncu);
+      const int64_t cap = (int64_t)bpc * b->ncu;
+      L.grid = (int)(units >= cap ? cap : std::min(cap, grid_bucket(units)));
       L.dynamic = s.dynamic;
     }
     if (L.grid < 1) L.grid = 1;
@@ -236,6 +252,16 @@ cog_status run_graph(cog_batch *b, const std::vector<Launch> &launches) {
   for (GraphEntry &g : b->graphs)
     if (g.key == key) ge = &g;
   if (!ge) {
+    // a launch set is captured the second time it occurs: one-off sets (a
+    // serving tick of unusual size) launch directly instead of paying for an
+    // instantiation they would never reuse
+    auto it = std::find(b->seen.begin(), b->seen.end(), key);
+    if (it == b->seen.end()) {
+      if ((int)b->seen.size() == kMaxSeen) b->seen.erase(b->seen.begin());
+      b->seen.push_back(key);
+      return launch_all(b, launches);
+    }
+    b->seen.erase(it);
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bhip(e, "graph capture");
     cog_status s = launch_all(b, launches);

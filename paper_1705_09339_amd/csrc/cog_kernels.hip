@@ -1399,10 +1399,10 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
 
           // S0 (frame difference) and S1 (running average) for every lane
           float dl = 0.0f;
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xq[c]));
           float dr2 = 0.0f;
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < C; ++c) {
             const float d = x[c] - rmu[c];
             dr2 = dr2 + d * d;
@@ -1419,16 +1419,16 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
           }
           {
             float nmu[C];
-  #pragma unroll
+#pragma unroll
             for (int c = 0; c < C; ++c) nmu[c] = kp.one_m_alpha_rga * rmu[c] + kp.alpha_rga * x[c];
             float sr = 0.0f;
-  #pragma unroll
+#pragma unroll
             for (int c = 0; c < C; ++c) {
               const float e = x[c] - nmu[c];
               sr = sr + e * e;
             }
             const float nvar = fmaxf(kp.var_min, kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr);
-  #pragma unroll
+#pragma unroll
             for (int c = 0; c < C; ++c) rmu[c] = s1 ? nmu[c] : rmu[c];
             rvar = s1 ? nvar : rvar;
           }
@@ -1465,13 +1465,13 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
                 // background from the mixture: the running average takes the
                 // matched component (the transition update of the active level)
                 float sv = m.var[0];
-  #pragma unroll
+#pragma unroll
                 for (int c = 0; c < C; ++c) rmu[c] = m.mu[0][c];
-  #pragma unroll
+#pragma unroll
                 for (int kk = 1; kk < K; ++kk) {
                   if (mp == kk) {
                     sv = m.var[kk];
-  #pragma unroll
+#pragma unroll
                     for (int c = 0; c < C; ++c) rmu[c] = m.mu[kk][c];
                   }
                 }
@@ -1481,7 +1481,7 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
             }
           }
         } else {
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < C; ++c) x[c] = xq[c];
         }
         // masks are streamed out: non-temporal (cache policy bit 1)
