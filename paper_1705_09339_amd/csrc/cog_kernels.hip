@@ -472,15 +472,12 @@ __device__ __forceinline__ int quant(float v, const KParams &kp) {
   }
 }
 
+// max_c |x_c - xp_c| (a NaN difference is skipped, as by the comparison form)
 template <int C>
 __device__ __forceinline__ float frame_delta(const float (&x)[C], const float (&xp)[C]) {
   float dl = 0.0f;
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    float d = x[c] - xp[c];
-    d = d < 0.0f ? -d : d;
-    dl = d > dl ? d : dl;
-  }
+  for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xp[c]));
   return dl;
 }
 
@@ -611,9 +608,11 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
       if (j >= 1) {
         if constexpr (with_prior) {
           const float dl = frame_delta<C>(x, xp);
-          if (dl < kp.res_e1) cnt0++;
-          else if (dl < kp.res_e2) cnt1++;
-          else cnt2++;
+          // residue bins [0, e1), [e1, e2), [e2, inf) counted without branches
+          const bool r0 = dl < kp.res_e1, r1 = !r0 && dl < kp.res_e2;
+          cnt0 += r0 ? 1u : 0u;
+          cnt1 += r1 ? 1u : 0u;
+          cnt2 += (!r0 && !r1) ? 1u : 0u;
         }
         int l, mp;
         mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
