@@ -1370,10 +1370,12 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
     wave_sync();
     in.issue(fr.x, fr.stride, fr.nframes, f0 + NB, tile0, npx, lane);
     const int nk = fr.nframes - f0 < NB ? fr.nframes - f0 : NB;
-    // this block's masks and statistics rows (frame k at soffset k * row)
+    // this block's masks and statistics rows (frame k at soffset k * row);
+    // the record count is an unsigned 32-bit field: at most 8 * 2^28 = 2^31
+    // mask bytes (frames are limited to 2^28 pixels)
     const __amdgpu_buffer_rsrc_t mr = __builtin_amdgcn_make_buffer_rsrc(
         fr.mask ? fr.mask + (int64_t)f0 * fr.mstride : nullptr, (short)0,
-        fr.mask ? (int)(nk * fr.mstride) : 0, 0x00020000);
+        fr.mask ? (int)(uint32_t)((uint64_t)nk * (uint64_t)fr.mstride) : 0, 0x00020000);
     const __amdgpu_buffer_rsrc_t sr = __builtin_amdgcn_make_buffer_rsrc(
         fr.partials ? fr.partials + (int64_t)f0 * fr.nslots * kStat : nullptr, (short)0,
         fr.partials ? nk * srow : 0, 0x00020000);

@@ -6,7 +6,8 @@ colour-gradient background, a bimodal square alternating between two colours,
 moving flat-colour rectangles for the foreground, per-pixel Gaussian noise
 rounded and clipped to u8), drawn with torch on the device.  The results
 depend on the torch version's random-number kernels, so these frames serve
-timing runs only; parity tests use synth.video.
+timing runs, and the one parity test whose frames are too large to draw on
+the host (the maximum frame size), which hands the oracle the same bytes.
 
 Nothing here implements any part of the background-subtraction method.
 """
