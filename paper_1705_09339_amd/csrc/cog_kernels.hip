@@ -1532,10 +1532,11 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
 }
 
 // Waves per SIMD the one-wave cascade kernels are held to: five for u8 input
-// up to K=5 (at most 96 VGPRs, every wave of a 640x480 frame resident); the
-// sampling variant's extra live state needs the 128-VGPR budget of four.
+// up to K=5 (at most 96 VGPRs, every wave of a 640x480 frame resident; with
+// frames handled in pairs the kernels need 76, the sampling variant 78).
 __host__ __device__ constexpr int cascade_min_waves(bool f32, int K, bool samp) {
-  return (!f32 && K <= 5) ? (samp ? 4 : 5) : 1;
+  (void)samp;
+  return (!f32 && K <= 5) ? 5 : 1;
 }
 
 template <int C, int K, bool F32, bool LP, bool SAMP>
