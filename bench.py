@@ -114,8 +114,9 @@ def pct(a, q):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the method has no cross-GPU exchange and this "
-              "build measures the single-GPU kernel (see the sharding notes in DESIGN.md).",
+        print("bench.py runs on one GPU only: pixels are independent, so the method has no "
+              "cross-GPU exchange; one stream would shard by row bands and many streams by "
+              "placing whole streams on GPUs, each GPU running the kernels measured here.",
               file=sys.stderr)
         sys.exit(2)
     import torch
