@@ -143,12 +143,15 @@ def main():
     stream = torch.cuda.current_stream()
     masks = torch.empty((F, P), dtype=torch.uint8, device="cuda")
 
-    def make(path, sample=False):
+    def make_params(path, sample=False):
         p = C.cog_default_params(spec.width, spec.height, 3, C.COG_U8, K, path=path,
                                  tile_px=args.tile)
         if sample:
             p.stage_mask = C.COG_STAGE_ALL | C.COG_STAGE_SAMPLE
-        return C.CogStream(p, stream=stream)
+        return p
+
+    def make(path, sample=False):
+        return C.CogStream(make_params(path, sample), stream=stream)
 
     chunk = args.chunk or F
 
@@ -301,7 +304,9 @@ def main():
     roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "alg_bytes_per_launch": int(dom_bytes), "launch_ms": round(dom_ms, 4)}
+            "alg_bytes_per_launch": int(dom_bytes), "launch_ms": round(dom_ms, 4),
+            # the stream's device state, beside the 256 MB last-level cache
+            "state_mb": round(C.cog_state_bytes(make_params(C.COG_PATH_CASCADE)) / 1e6, 1)}
     if traffic:
         roof["traffic_note"] = traffic["note"]
 
