@@ -1281,6 +1281,8 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
 //    back once at the end of the launch;
 //  - the input is block-staged through LDS (InStage): the global-memory wait
 //    is paid once per block of frames, on loads issued a block earlier;
+//  - frames go two per loop iteration, the input alternating between two
+//    register arrays, so the previous value is never copied;
 //  - the mask and statistics stores are bounds-checked buffer stores;
 //  - for u8 input up to K = 5 the register budget keeps five waves per SIMD (a 640x480
 //    frame is 4.7 waves per SIMD: all of them stay resident).
