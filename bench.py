@@ -107,6 +107,23 @@ def measured_traffic(kernel, workload):
     return {"bytes_per_launch": b, "note": kv.get("note", "")}
 
 
+def measured_valu(kernel, workload):
+    """Wave64 VALU instructions per launch of `kernel` from the committed SQ
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"valu_issue_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    src = None
+    for line in open(path):
+        if line.startswith("# kernel_source_sha256:"):
+            src = line.split(":", 1)[1].strip()
+        elif not line.startswith("#") and line.startswith(kernel + "<3, 5, false, true, false>"):
+            if src != kernel_source_hash():
+                return None
+            return int(line[line.index(">") + 1:].split()[1])  # dur_us, VALU, ...
+    return None
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
@@ -309,6 +326,13 @@ def main():
             "state_mb": round(C.cog_state_bytes(make_params(C.COG_PATH_CASCADE)) / 1e6, 1)}
     if traffic:
         roof["traffic_note"] = traffic["note"]
+    # the kernel is limited by instruction issue rather than HBM: its VALU
+    # instructions (committed counters) against one wave64 instruction per 4
+    # cycles per SIMD, 1024 SIMDs at 2.4 GHz, over the live launch time
+    valu = measured_valu(dominant, spec.name) if K == 5 else None
+    if valu:
+        roof["valu_instructions"] = valu
+        roof["valu_issue_frac"] = round(valu * 4 / (1024 * 2.4e9) / (dom_ms * 1e-3), 4)
 
     res = {
         "metric": METRIC,
