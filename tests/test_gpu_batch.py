@@ -310,3 +310,21 @@ def test_more_than_eight_classes_rejected(C, S):
         for s, _ in ctxs:
             s.close()
         b.close()
+
+
+def test_batch_equals_alone_full_size_streams(C, S):
+    """Full-size streams (1280x720 and 640x480 at K=5, 320x240 at K=3, one
+    joining late) through the same tick plan: launch shapes like the
+    64-stream workload's, with multi-frame ticks staging the prior in LDS and
+    graphs captured once a launch set repeats; every stream equals its alone
+    run bit for bit."""
+    streams = [
+        ("u8c3k5-1280x720", gpu_params(C, 1280, 720, c=3, K=5), _synth(1280, 720, 50, 20, 11), 20, 0),
+        ("u8c3k5-640x480", gpu_params(C, 640, 480, c=3, K=5), _synth(640, 480, 60, 20, 12), 20, 2),
+        ("u8c3k3-320x240", gpu_params(C, 320, 240, c=3, K=3), _synth(320, 240, 70, 20, 13), 20, 0),
+    ]
+    plan, used = tick_plan(streams)
+    say("full-size batch: frames used", used)
+    alone = run_alone(C, S, streams, plan)
+    batched = run_batched(C, S, streams, plan)
+    assert_same(streams, alone, batched)
