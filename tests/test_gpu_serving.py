@@ -234,3 +234,42 @@ def test_concurrent_submitters_and_poller(C):
     for i in range(2):
         assert np.array_equal(masks[i].cpu().numpy(), ref[i][0])
         assert states[i] == ref[i][1]
+
+
+def test_serving_full_size_streams_equal_alone(C):
+    """A 1920x1080 and a 640x480 stream (K=5) served together, one frame per
+    submission, the second admitted while the first runs: masks and state
+    equal each stream alone, bit for bit."""
+    import torch
+    specs = [(1920, 1080, 32, 21), (640, 480, 40, 22)]
+    streams = [(gpu_params(C, w, h, c=3, K=5), _synth(w, h, n, s)) for w, h, n, s in specs]
+    devs = [torch.from_numpy(np.ascontiguousarray(fr)).cuda() for _, fr in streams]
+    torch.cuda.synchronize()
+    ref = [alone(C, p, d, 20) for (p, _), d in zip(streams, devs)]
+    masks = [torch.zeros((d.shape[0] - 20, p.width * p.height), dtype=torch.uint8, device="cuda")
+             for (p, _), d in zip(streams, devs)]
+    torch.cuda.synchronize()
+    srv = C.CogServer(hbm_budget=4 << 30, max_streams=4, depth=2)
+    ids = {0: srv.open(streams[0][0], devs[0][:20])}
+    nxt = {0: 0}  # next frame of each stream (after its training frames)
+    tag = 0
+    for step in range(max(d.shape[0] for d in devs) - 20 + 3):
+        if step == 3:
+            ids[1] = srv.open(streams[1][0], devs[1][:20])
+            nxt[1] = 0
+        for i in ids:
+            f = nxt[i]
+            if f < devs[i].shape[0] - 20:
+                srv.submit(ids[i], devs[i][20 + f:21 + f], masks[i][f:f + 1], tag=tag, nframes=1)
+                nxt[i] = f + 1
+                tag += 1
+    srv.drain()
+    comps = srv.poll(max_n=tag + 8)
+    assert len(comps) == tag and all(c["status"] == 0 for c in comps)
+    states = {i: srv.export_state(ids[i]) for i in ids}
+    for i in ids:
+        srv.close_stream(ids[i])
+    srv.close()
+    for i in range(2):
+        assert np.array_equal(masks[i].cpu().numpy(), ref[i][0]), i
+        assert states[i] == ref[i][1], i
