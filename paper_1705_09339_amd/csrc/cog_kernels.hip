@@ -1318,6 +1318,7 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
   const bool fd_on = (kp.stage_mask & 1u) != 0;
   const bool rga_on = (kp.stage_mask & 2u) != 0;
   const bool kde_on = (kp.stage_mask & 4u) != 0;
+  const bool tau_zero = kp.tau_fd == 0.0f;
 
   float xp[C], rmu[C], rvar = 0.0f;
   // per-lane flags kept as integers (0/1) so that branch joins cost no
@@ -1400,17 +1401,27 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
         if (!halted) {
           Stage::read_mis(s_in, k, mis, lane, x);
 
-          // S0 (frame difference) and S1 (running average) for every lane
-          float dl = 0.0f;
+          // S0 (frame difference) and S1 (running average) for every lane;
+          // with u8 input and a zero tolerance S0 is plain equality, and the
+          // difference itself is formed only for survivors
+          bool fd_ok;
+          if (!F32 && tau_zero) {
+            fd_ok = true;
 #pragma unroll
-          for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xq[c]));
+            for (int c = 0; c < C; ++c) fd_ok = fd_ok && x[c] == xq[c];
+          } else {
+            float d0 = 0.0f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) d0 = fmaxf(d0, fabsf(x[c] - xq[c]));
+            fd_ok = d0 <= kp.tau_fd;
+          }
           float dr2 = 0.0f;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             const float d = x[c] - rmu[c];
             dr2 = dr2 + d * d;
           }
-          const bool s0 = fd_on && dl <= kp.tau_fd;
+          const bool s0 = fd_on && fd_ok;
           const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * rvar;
           if constexpr (SAMP) {
             // confident: decided by the frame difference, or by the running
@@ -1430,7 +1441,11 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
               const float e = x[c] - nmu[c];
               sr = sr + e * e;
             }
-            const float nvar = fmaxf(kp.var_min, kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr);
+            const float nv = kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr;
+            // u8 input keeps both operands positive and finite, where the
+            // larger binary32 is the larger bit pattern
+            const float nvar = F32 ? fmaxf(kp.var_min, nv)
+                                   : __int_as_float(max(__float_as_int(kp.var_min), __float_as_int(nv)));
 #pragma unroll
             for (int c = 0; c < C; ++c) rmu[c] = s1 ? nmu[c] : rmu[c];
             rvar = s1 ? nvar : rvar;
@@ -1450,6 +1465,9 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
             float conf = 0.0f;
             bool accept = false;
             if (kde_on) {
+              float dl = 0.0f;
+#pragma unroll
+              for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xq[c]));
               conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
               accept = conf >= kp.conf_thr;
             }
