@@ -133,4 +133,21 @@ hipError_t launch_group_map(const uint2 *keys, int64_t P, const uint8_t *asg, co
 // (0 if the query fails).
 int tick_blocks_per_cu(int C, int K, bool f32in, bool lp, bool samp);
 
+// The same launchers for one mixture size K (cog_kern.h), instantiated for
+// K = 1..8, one translation unit each; the calls above dispatch on K.
+template <int K>
+hipError_t launch_train_k(int C, bool f32in, bool prior, const Buffers &b, const void *frames,
+                          int64_t stride, int n, const KParams &kp, hipStream_t s);
+template <int K>
+hipError_t launch_cascade_k(int C, bool f32in, int tile, const Buffers &b, const Frames &fr,
+                            const KParams &kp, hipStream_t s);
+template <int K>
+hipError_t launch_tick_k(int C, bool f32in, bool lp, bool samp, TickHead *head,
+                         const TickItem *items, int grid, int dynamic, hipStream_t s);
+template <int K>
+int tick_blocks_per_cu_k(int C, bool f32in, bool lp, bool samp);
+template <int K>
+hipError_t launch_gmm_k(int C, bool f32in, const Buffers &b, const Frames &fr, const KParams &kp,
+                        hipStream_t s);
+
 }  // namespace cog
