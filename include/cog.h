@@ -205,6 +205,23 @@ typedef struct {
 cog_status cog_group_background(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,
                                 cog_group_info *info);
 
+/* The same grouping without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Its scratch (assignment and map planes, per-block sums)
+ * is a static device array of about 20 MiB that every GPU the library runs on
+ * holds until the process ends; its address is looked up per GPU by
+ * cog_create.  Streams of at most COG_NOALLOC_MAX_PIXELS pixels, else
+ * COG_E_INVALID; COG_E_DEVICE if the scratch could not be located.  Every
+ * call on one GPU shares that GPU's scratch and leaves its contents behind
+ * (each call initialises what it reads): calls that overlap on one GPU, from
+ * several host threads or on several streams, race, and the caller must
+ * serialise them.  Arguments, results and errors otherwise as
+ * cog_group_background; synchronous. */
+#define COG_NOALLOC_MAX_PIXELS (1 << 23)
+cog_status cog_group_background_noalloc(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,
+                                        cog_group_info *info);
+
+
 /* Integer prior kernel weights W[b][v] (16 x 256, row-major) for bandwidth h,
  * as used by the training kernel; host-only, needs no GPU. */
 cog_status cog_kde_weights(float h, uint16_t *out);

@@ -132,6 +132,7 @@ def _load(path: str = LIB_PATH):
         "cog_kde_weights": ([ct.c_float, P(ct.c_uint16)], ct.c_int),
         "cog_last_error": ([V], ct.c_char_p),
         "cog_group_background": ([V, V, ct.c_int32, P(cog_group_info)], ct.c_int),
+        "cog_group_background_noalloc": ([V, V, ct.c_int32, P(cog_group_info)], ct.c_int),
         "cog_batch_create": ([V, ct.c_int32, P(V)], ct.c_int),
         "cog_batch_tick": ([V, P(cog_tick_item), ct.c_int32], ct.c_int),
         "cog_batch_autotune": ([V, P(cog_tick_item), ct.c_int32, ct.c_int32, P(cog_schedule)], ct.c_int),
@@ -160,7 +161,7 @@ lib = _load()
 EXPORTED = ("cog_default_params", "cog_state_bytes", "cog_canonical_bytes", "cog_create",
             "cog_train_prior", "cog_step", "cog_step_frames", "cog_reset", "cog_destroy",
             "cog_export_state", "cog_import_state", "cog_kde_weights", "cog_last_error",
-            "cog_group_background",
+            "cog_group_background", "cog_group_background_noalloc",
             "cog_batch_create", "cog_batch_tick", "cog_batch_autotune", "cog_batch_set_schedule",
             "cog_batch_get_schedule", "cog_batch_destroy",
             "cog_server_create", "cog_server_open", "cog_server_submit", "cog_server_close",
@@ -293,6 +294,19 @@ def cog_group_background(h: int, map_out=None) -> dict:
     _check(lib.cog_group_background(h, mp, mdev, ct.byref(info)), h)
     del keep
     return info.as_dict()
+
+
+def cog_group_background_noalloc(h: int, map_out=None) -> dict:
+    """cog_group_background on the library's static device scratch (no
+    device allocation; streams of at most COG_NOALLOC_MAX_PIXELS pixels)."""
+    mp, mdev, keep = _ptr(map_out)
+    info = cog_group_info()
+    _check(lib.cog_group_background_noalloc(h, mp, mdev, ct.byref(info)), h)
+    del keep
+    return info.as_dict()
+
+
+COG_NOALLOC_MAX_PIXELS = 1 << 23
 
 
 def cog_last_error(h: Optional[int] = None) -> str:

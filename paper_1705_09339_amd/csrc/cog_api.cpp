@@ -267,6 +267,106 @@ cog_status run_frames(cog_ctx *h, const void *dframes, int n, uint8_t *dmasks, b
   return COG_OK;
 }
 
+// Grouping preconditions shared by both entry points.
+cog_status group_check(cog_ctx *h) {
+  if (!h) return fail(nullptr, COG_E_INVALID, "context is NULL");
+  if (h->p.path != COG_PATH_CASCADE) return fail(h, COG_E_UNSUPPORTED, "grouping needs the cascade path");
+  if (h->n_train == 0) return fail(h, COG_E_STATE, "cog_train_prior has not run");
+  return COG_OK;
+}
+
+// The grouping on caller-provided device scratch: asg and smap P bytes each
+// (smap used when map_out is not a device buffer), part group_blocks(P) *
+// kGroupStat words, red kGroupStat words.  Every per-block row is reduced on
+// the device, so the host reads a few words per pass into its stack.
+cog_status group_run(cog_ctx *h, uint8_t *map_out, int32_t map_on_device, cog_group_info *info,
+                     uint8_t *asg, uint8_t *smap, uint64_t *part, uint64_t *red) {
+  const int64_t P = h->plan.P;
+  const int nb = cog::group_blocks(P);
+  const uint2 *keys = h->buf.gkey;
+  hipStream_t st = h->stream;
+  cog_status rc = COG_OK;
+  uint64_t row[cog::kGroupStat];
+  auto check = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess && rc == COG_OK) rc = hip_fail(h, e, what);
+    return rc == COG_OK;
+  };
+  auto reduce = [&](int width, uint32_t minmask, uint32_t maxmask) {
+    return check(cog::launch_part_reduce(part, nb, width, minmask, maxmask, red, st), "grouping launch") &&
+           check(hipMemcpyAsync(row, red, (size_t)width * 8, hipMemcpyDeviceToHost, st), "copy") &&
+           check(hipStreamSynchronize(st), "grouping");
+  };
+  uint8_t *dmap = map_out && map_on_device ? map_out : smap;
+  cog::GroupCenters c{};
+  cog::GroupBands bands{};
+  int it = 0;
+  uint64_t cnt[cog::kGroups] = {0}, s1[cog::kGroups][2] = {{0}}, s2[cog::kGroups][2] = {{0}};
+  // initial centres: minimum, floor of the mean, maximum of each key
+  // (per-block rows {min, max, sum} for each key)
+  if (check(cog::launch_group_range(keys, P, part, st), "grouping launch") &&
+      reduce(6, 0x9u, 0x12u)) {
+    for (int d = 0; d < 2; ++d) {
+      c.c[0][d] = (int64_t)row[3 * d];
+      c.c[1][d] = (int64_t)(row[3 * d + 2] / (uint64_t)P);
+      c.c[2][d] = (int64_t)row[3 * d + 1];
+    }
+  }
+  if (rc == COG_OK) check(cog::launch_fill_u8(asg, P, 255, st), "grouping launch");
+  // Lloyd passes until no assignment changes
+  for (it = 1; rc == COG_OK && it <= 32; ++it) {
+    if (!check(cog::launch_group_assign(keys, P, c, asg, part, st), "grouping launch") ||
+        !reduce(cog::kGroupStat, 0u, 0u))
+      break;
+    const uint64_t changed = row[0];
+    for (int g = 0; g < cog::kGroups; ++g) {
+      cnt[g] = row[1 + 5 * g];
+      s1[g][0] = row[2 + 5 * g];
+      s1[g][1] = row[3 + 5 * g];
+      s2[g][0] = row[4 + 5 * g];
+      s2[g][1] = row[5 + 5 * g];
+    }
+    if (changed == 0) break;
+    for (int g = 0; g < cog::kGroups; ++g)
+      if (cnt[g])
+        for (int d = 0; d < 2; ++d) c.c[g][d] = (int64_t)(s1[g][d] / cnt[g]);
+  }
+  if (it > 32) it = 32;
+  // eq. 3: one standard deviation around each cluster's member mean
+  for (int g = 0; g < cog::kGroups; ++g)
+    for (int d = 0; d < 2; ++d) {
+      if (!cnt[g]) {
+        bands.mean[g][d] = bands.sd[g][d] = 0.0;
+        continue;
+      }
+      const double n = (double)cnt[g];
+      bands.mean[g][d] = (double)s1[g][d] / n;
+      const double var = (double)s2[g][d] / n - bands.mean[g][d] * bands.mean[g][d];
+      bands.sd[g][d] = var > 0.0 ? std::sqrt(var) : 0.0;
+    }
+  if (rc == COG_OK)
+    check(cog::launch_group_map(keys, P, asg, bands, dmap, info ? part : nullptr, st),
+          "grouping launch");
+  if (rc == COG_OK && info) reduce(cog::kGroups, 0u, 0u);
+  if (rc == COG_OK && map_out && !map_on_device)
+    check(hipMemcpyAsync(map_out, dmap, (size_t)P, hipMemcpyDeviceToHost, st), "copy");
+  if (rc == COG_OK) check(hipStreamSynchronize(st), "grouping");
+  if (rc == COG_OK && info) {
+    std::memset(info, 0, sizeof(*info));
+    info->iterations = it;
+    for (int g = 0; g < cog::kGroups; ++g) {
+      cog_group_stats &o = info->group[g];
+      o.count = (int64_t)cnt[g];
+      o.grouped = (int64_t)row[g];
+      for (int d = 0; d < 2; ++d) {
+        o.center[d] = c.c[g][d];
+        o.mean[d] = bands.mean[g][d];
+        o.sd[d] = bands.sd[g][d];
+      }
+    }
+  }
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -396,6 +496,14 @@ cog_status cog_create(const cog_params *p, void *hip_stream, void *device_state,
     return s;
   }
   h->kp = make_kparams(p, 2);
+  // the device address of this GPU's no-allocation scratch, looked up while
+  // the GPU is current (only cog_group_background_noalloc needs it)
+  he = cog::scratch_for_device(dev, &h->scratch);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    h->scratch = nullptr;
+    h->scratch_err = hipGetErrorString(he);
+  }
   *out = h;
   return COG_OK;
 }
@@ -653,117 +761,38 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
 
 cog_status cog_group_background(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,
                                 cog_group_info *info) {
-  if (!h) return fail(nullptr, COG_E_INVALID, "context is NULL");
-  if (h->p.path != COG_PATH_CASCADE) return fail(h, COG_E_UNSUPPORTED, "grouping needs the cascade path");
-  if (h->n_train == 0) return fail(h, COG_E_STATE, "cog_train_prior has not run");
+  cog_status s = group_check(h);
+  if (s != COG_OK) return s;
   const int64_t P = h->plan.P;
-  const int nb = cog::group_blocks(P);
-  const size_t part_words = (size_t)nb * cog::kGroupStat;
-  uint8_t *asg = nullptr, *dmap = nullptr;
+  const size_t part_words = (size_t)cog::group_blocks(P) * cog::kGroupStat;
+  uint8_t *asg = nullptr;
   uint64_t *part = nullptr;
-  const uint2 *keys = h->buf.gkey;
-  hipStream_t st = h->stream;
-  cog_status rc = COG_OK;
-  std::vector<uint64_t> hp(part_words);
-  std::vector<uint8_t> hmap;
-  auto check = [&](hipError_t e, const char *what) {
-    if (e != hipSuccess && rc == COG_OK) rc = hip_fail(h, e, what);
-    return rc == COG_OK;
-  };
-  auto fetch = [&](size_t words) {
-    return check(hipMemcpyAsync(hp.data(), part, words * 8, hipMemcpyDeviceToHost, st), "copy") &&
-           check(hipStreamSynchronize(st), "grouping");
-  };
   if (hipMalloc((void **)&asg, (size_t)P * 2) != hipSuccess ||
-      hipMalloc((void **)&part, part_words * 8) != hipSuccess) {
+      hipMalloc((void **)&part, (part_words + cog::kGroupStat) * 8) != hipSuccess) {
     (void)hipGetLastError();
     if (asg) (void)hipFree(asg);
     return fail(h, COG_E_OOM, "grouping scratch allocation failed");
   }
-  dmap = map_out && map_on_device ? map_out : asg + P;
-  cog::GroupCenters c{};
-  cog::GroupBands bands{};
-  int it = 0;
-  uint64_t cnt[cog::kGroups] = {0}, s1[cog::kGroups][2] = {{0}}, s2[cog::kGroups][2] = {{0}};
-  // initial centres: minimum, floor of the mean, maximum of each key
-  if (check(cog::launch_group_range(keys, P, part, st), "grouping launch") && fetch((size_t)nb * 6)) {
-    for (int d = 0; d < 2; ++d) {
-      uint64_t lo = ~0ull, hi = 0, sum = 0;
-      for (int b = 0; b < nb; ++b) {
-        lo = std::min(lo, hp[(size_t)b * 6 + 3 * d]);
-        hi = std::max(hi, hp[(size_t)b * 6 + 3 * d + 1]);
-        sum += hp[(size_t)b * 6 + 3 * d + 2];
-      }
-      c.c[0][d] = (int64_t)lo;
-      c.c[1][d] = (int64_t)(sum / (uint64_t)P);
-      c.c[2][d] = (int64_t)hi;
-    }
-  }
-  if (rc == COG_OK) check(hipMemsetAsync(asg, 255, (size_t)P, st), "grouping");
-  // Lloyd passes until no assignment changes
-  for (it = 1; rc == COG_OK && it <= 32; ++it) {
-    if (!check(cog::launch_group_assign(keys, P, c, asg, part, st), "grouping launch") ||
-        !fetch(part_words))
-      break;
-    uint64_t changed = 0;
-    for (int g = 0; g < cog::kGroups; ++g) cnt[g] = s1[g][0] = s1[g][1] = s2[g][0] = s2[g][1] = 0;
-    for (int b = 0; b < nb; ++b) {
-      const uint64_t *r = hp.data() + (size_t)b * cog::kGroupStat;
-      changed += r[0];
-      for (int g = 0; g < cog::kGroups; ++g) {
-        cnt[g] += r[1 + 5 * g];
-        s1[g][0] += r[2 + 5 * g];
-        s1[g][1] += r[3 + 5 * g];
-        s2[g][0] += r[4 + 5 * g];
-        s2[g][1] += r[5 + 5 * g];
-      }
-    }
-    if (changed == 0) break;
-    for (int g = 0; g < cog::kGroups; ++g)
-      if (cnt[g])
-        for (int d = 0; d < 2; ++d) c.c[g][d] = (int64_t)(s1[g][d] / cnt[g]);
-  }
-  if (it > 32) it = 32;
-  // eq. 3: one standard deviation around each cluster's member mean
-  for (int g = 0; g < cog::kGroups; ++g)
-    for (int d = 0; d < 2; ++d) {
-      if (!cnt[g]) {
-        bands.mean[g][d] = bands.sd[g][d] = 0.0;
-        continue;
-      }
-      const double n = (double)cnt[g];
-      bands.mean[g][d] = (double)s1[g][d] / n;
-      const double var = (double)s2[g][d] / n - bands.mean[g][d] * bands.mean[g][d];
-      bands.sd[g][d] = var > 0.0 ? std::sqrt(var) : 0.0;
-    }
-  if (rc == COG_OK) check(cog::launch_group_map(keys, P, asg, bands, dmap, st), "grouping launch");
-  if (rc == COG_OK && (info || (map_out && !map_on_device))) {
-    hmap.resize((size_t)P);
-    check(hipMemcpyAsync(hmap.data(), dmap, (size_t)P, hipMemcpyDeviceToHost, st), "copy");
-  }
-  if (rc == COG_OK) check(hipStreamSynchronize(st), "grouping");
-  if (rc == COG_OK && map_out && !map_on_device) std::memcpy(map_out, hmap.data(), (size_t)P);
-  if (rc == COG_OK && info) {
-    std::memset(info, 0, sizeof(*info));
-    info->iterations = it;
-    int64_t grouped[cog::kGroups] = {0, 0, 0};
-    for (int64_t i = 0; i < P; ++i)
-      if (hmap[(size_t)i] < cog::kGroups) grouped[hmap[(size_t)i]]++;
-    for (int g = 0; g < cog::kGroups; ++g) {
-      cog_group_stats &o = info->group[g];
-      o.count = (int64_t)cnt[g];
-      o.grouped = grouped[g];
-      for (int d = 0; d < 2; ++d) {
-        o.center[d] = c.c[g][d];
-        o.mean[d] = bands.mean[g][d];
-        o.sd[d] = bands.sd[g][d];
-      }
-    }
-  }
-  (void)hipStreamSynchronize(st);
+  s = group_run(h, map_out, map_on_device, info, asg, asg + P, part, part + part_words);
+  (void)hipStreamSynchronize(h->stream);
   (void)hipFree(asg);
   (void)hipFree(part);
-  return rc;
+  return s;
+}
+
+cog_status cog_group_background_noalloc(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,
+                                        cog_group_info *info) {
+  cog_status s = group_check(h);
+  if (s != COG_OK) return s;
+  if (h->plan.P > cog::kNoAllocMaxPixels)
+    return fail(h, COG_E_INVALID, "frame larger than the no-allocation scratch (at most " +
+                                      std::to_string(cog::kNoAllocMaxPixels) + " pixels)");
+  char *sc = h->scratch;
+  if (!sc) return fail(h, COG_E_DEVICE, "no-allocation scratch unavailable: " + h->scratch_err);
+  return group_run(h, map_out, map_on_device, info, reinterpret_cast<uint8_t *>(sc + cog::kScratchAsg),
+                   reinterpret_cast<uint8_t *>(sc + cog::kScratchMap),
+                   reinterpret_cast<uint64_t *>(sc + cog::kScratchPart),
+                   reinterpret_cast<uint64_t *>(sc + cog::kScratchRed));
 }
 
 const char *cog_last_error(const cog_ctx *h) {

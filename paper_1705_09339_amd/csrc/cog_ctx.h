@@ -49,4 +49,6 @@ struct cog_ctx {
   size_t stage_mask_cap = 0;
   std::vector<uint32_t> host_stats;
   std::string err;
+  char *scratch = nullptr;  // this GPU's no-allocation grouping scratch (device address)
+  std::string scratch_err;
 };

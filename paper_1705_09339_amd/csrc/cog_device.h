@@ -128,7 +128,26 @@ hipError_t launch_group_range(const uint2 *keys, int64_t P, uint64_t *part, hipS
 hipError_t launch_group_assign(const uint2 *keys, int64_t P, const GroupCenters &c, uint8_t *asg,
                                uint64_t *part, hipStream_t s);
 hipError_t launch_group_map(const uint2 *keys, int64_t P, const uint8_t *asg, const GroupBands &b,
-                            uint8_t *map, hipStream_t s);
+                            uint8_t *map, uint64_t *cnt, hipStream_t s);
+// out[f] = column f of part[nb][width] reduced by minimum (bit f of minmask),
+// maximum (maxmask) or sum; one workgroup.
+hipError_t launch_part_reduce(const uint64_t *part, int nb, int width, uint32_t minmask,
+                              uint32_t maxmask, uint64_t *out, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
+
+// Static scratch of the no-allocation grouping call: the assignment plane,
+// the map plane, per-block rows, the reduced row.
+constexpr int64_t kNoAllocMaxPixels = (int64_t)1 << 23;  // 8 Mpx: 3840 x 2160 fits
+constexpr size_t kScratchAsg = 0;
+constexpr size_t kScratchMap = (size_t)kNoAllocMaxPixels;
+constexpr size_t kScratchPart = 2 * (size_t)kNoAllocMaxPixels;
+constexpr size_t kScratchRed =
+    kScratchPart + (size_t)(kNoAllocMaxPixels / kNT) * kGroupStat * sizeof(uint64_t);
+constexpr size_t kNoAllocScratchBytes = kScratchRed + 256;
+// Device address of GPU `device`'s copy of the scratch; the first call for a
+// GPU must have that GPU current.
+constexpr int kMaxDevices = 64;
+hipError_t scratch_for_device(int device, char **out);
 // Workgroups of the class's tick kernel one compute unit keeps resident
 // (0 if the query fails).
 int tick_blocks_per_cu(int C, int K, bool f32in, bool lp, bool samp);

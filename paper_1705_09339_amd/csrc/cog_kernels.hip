@@ -5,6 +5,8 @@
 // cog_inst_k*.hip).
 #include "cog_device.h"
 
+#include <mutex>
+
 namespace cog {
 namespace {
 
@@ -149,20 +151,94 @@ __global__ __launch_bounds__(kNT) void k_group_assign(const uint2 *keys, int64_t
   if (threadIdx.x < kGroupStat) part[(int64_t)blockIdx.x * kGroupStat + threadIdx.x] = out[threadIdx.x];
 }
 
+// The final map, and (cnt != nullptr) per-block counts of the grouped
+// pixels of each cluster ([blocks][kGroups] u64).
 __global__ __launch_bounds__(kNT) void k_group_map(const uint2 *keys, int64_t P, const uint8_t *asg,
-                                                   GroupBands bands, uint8_t *map) {
+                                                   GroupBands bands, uint8_t *map, uint64_t *cnt) {
+  __shared__ uint64_t red[kNW];
   const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
-  if (p >= P) return;
-  const uint2 k = keys[p];
-  const int g = asg[p];
-  bool in = true;
+  const bool valid = p < P;
+  int g = 0;
+  bool in = false;
+  if (valid) {
+    const uint2 k = keys[p];
+    g = asg[p];
+    in = true;
 #pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    const double e = (double)(d ? k.y : k.x) - bands.mean[g][d];
-    in = in && (fabs(e) <= bands.sd[g][d]);
+    for (int d = 0; d < 2; ++d) {
+      const double e = (double)(d ? k.y : k.x) - bands.mean[g][d];
+      in = in && (fabs(e) <= bands.sd[g][d]);
+    }
+    map[p] = in ? (uint8_t)g : (uint8_t)255;
   }
-  map[p] = in ? (uint8_t)g : (uint8_t)255;
+  if (cnt) {  // uniform
+    uint64_t out[kGroups];
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) out[q] = block_sum_u64(in && g == q ? 1ull : 0ull, red);
+    if (threadIdx.x < kGroups) cnt[(int64_t)blockIdx.x * kGroups + threadIdx.x] = out[threadIdx.x];
+  }
 }
+
+// Column reduction of per-block rows [nb][width] (width <= kGroupStat) into
+// out[width] by one workgroup: field f is a minimum when bit f of minmask is
+// set, a maximum for maxmask, else a sum.  Integer, so order-independent.
+__global__ __launch_bounds__(kNT) void k_part_reduce(const uint64_t *part, int nb, int width,
+                                                     uint32_t minmask, uint32_t maxmask,
+                                                     uint64_t *out) {
+  __shared__ uint64_t red[kNW][kGroupStat];
+  uint64_t acc[kGroupStat];
+#pragma unroll
+  for (int f = 0; f < kGroupStat; ++f)
+    acc[f] = ((minmask >> f) & 1u) ? ~0ull : 0ull;
+  for (int i = threadIdx.x; i < nb; i += kNT) {
+#pragma unroll
+    for (int f = 0; f < kGroupStat; ++f) {
+      if (f >= width) break;
+      const uint64_t v = part[(int64_t)i * width + f];
+      if ((minmask >> f) & 1u) acc[f] = v < acc[f] ? v : acc[f];
+      else if ((maxmask >> f) & 1u) acc[f] = v > acc[f] ? v : acc[f];
+      else acc[f] += v;
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < kGroupStat; ++f) {
+    uint64_t v = acc[f];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint64_t w = (uint64_t)__shfl_xor((long long)v, o, 64);
+      if ((minmask >> f) & 1u) v = w < v ? w : v;
+      else if ((maxmask >> f) & 1u) v = w > v ? w : v;
+      else v += w;
+    }
+    acc[f] = v;
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int f = 0; f < kGroupStat; ++f) red[threadIdx.x >> 6][f] = acc[f];
+  }
+  __syncthreads();
+  if (threadIdx.x < width) {
+    const int f = threadIdx.x;
+    uint64_t v = red[0][f];
+    for (int w = 1; w < kNW; ++w) {
+      const uint64_t x = red[w][f];
+      if ((minmask >> f) & 1u) v = x < v ? x : v;
+      else if ((maxmask >> f) & 1u) v = x > v ? x : v;
+      else v += x;
+    }
+    out[f] = v;
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_fill_u8(uint8_t *p, int64_t n, uint8_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT)
+    p[i] = v;
+}
+
+// Scratch of the no-allocation grouping entry point: the assignment and map
+// planes of up to kNoAllocMaxPixels pixels, the per-block rows and the
+// reduced row.  One copy per GPU, held until the process ends.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
 
 }  // namespace
 
@@ -237,10 +313,47 @@ hipError_t launch_group_assign(const uint2 *keys, int64_t P, const GroupCenters 
 }
 
 hipError_t launch_group_map(const uint2 *keys, int64_t P, const uint8_t *asg, const GroupBands &b,
-                            uint8_t *map, hipStream_t s) {
+                            uint8_t *map, uint64_t *cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_group_map, dim3((unsigned)group_blocks(P)), dim3(kNT), 0, s, keys, P, asg, b,
-                     map);
+                     map, cnt);
   return hipGetLastError();
+}
+
+hipError_t launch_part_reduce(const uint64_t *part, int nb, int width, uint32_t minmask,
+                              uint32_t maxmask, uint64_t *out, hipStream_t s) {
+  if (width < 1 || width > kGroupStat || nb < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_part_reduce, dim3(1), dim3(kNT), 0, s, part, nb, width, minmask, maxmask, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + kNT - 1) / kNT;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)blocks), dim3(kNT), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// The scratch's device address is looked up once per GPU, with that GPU
+// current (every GPU holds its own copy at its own address), and kept; host
+// code uses only these addresses, never the array's name.
+hipError_t scratch_for_device(int device, char **out) {
+  static std::mutex mu;
+  static char *addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<char *>(ptr);
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_stats(const StatJob &job, hipStream_t s) {

@@ -144,6 +144,7 @@ def test_null_context_calls_are_invalid(C):
     assert C.lib.cog_step(None, None, 0, None, 0, None) == C.COG_E_INVALID
     assert C.lib.cog_train_prior(None, None, 10, 0) == C.COG_E_INVALID
     assert C.lib.cog_group_background(None, None, 0, None) == C.COG_E_INVALID
+    assert C.lib.cog_group_background_noalloc(None, None, 0, None) == C.COG_E_INVALID
     C.lib.cog_destroy(None)
 
 
