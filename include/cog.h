@@ -154,7 +154,15 @@ cog_status cog_step(cog_ctx *h, const void *frame, int32_t frame_on_device, uint
 /* n consecutive frames of one stream in one launch (n x H x W x C frames,
  * n x H x W masks).  The result is bit-identical to n cog_step() calls; the
  * per-pixel state stays in registers across the n frames.  infos (n entries)
- * may be NULL; when given the call waits.  1 <= n. */
+ * may be NULL; when given, per-tile counter rows (16 bytes per 64 pixels
+ * and frame) are reduced on the device and the call waits once at the end.
+ * The rows of up to 16..64 frames fit the state (32 MiB); a call over more
+ * frames grows a row workspace of the context, up to 1 GiB (hipMalloc on
+ * first use, kept until cog_destroy), so that its frames go in one launch
+ * (as many launches as the workspace needs; if the allocation fails, in
+ * launches of the state's chunk).  1 <= n.  With tile_px = 0 a single frame
+ * (n = 1, no sampling) runs the per-frame kernel: 256-pixel tiles whose
+ * survivors are compacted into one work list per wave. */
 cog_status cog_step_frames(cog_ctx *h, const void *frames, int32_t n, int32_t frames_on_device,
                            uint8_t *masks_out, int32_t masks_on_device, cog_step_info *infos);
 
@@ -221,7 +229,6 @@ cog_status cog_group_background(cog_ctx *h, uint8_t *map_out, int32_t map_on_dev
 cog_status cog_group_background_noalloc(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,
                                         cog_group_info *info);
 
-
 /* Integer prior kernel weights W[b][v] (16 x 256, row-major) for bandwidth h,
  * as used by the training kernel; host-only, needs no GPU. */
 cog_status cog_kde_weights(float h, uint16_t *out);
@@ -250,7 +257,9 @@ typedef struct {
   cog_ctx *ctx;           /* trained context, cascade path, 64-pixel tiles (tile_px 0 or 64) */
   const void *frames;     /* device: nframes x H x W x C, contiguous */
   uint8_t *masks;         /* device: nframes x H x W, or NULL */
-  int32_t nframes;        /* >= 0 (0: the item is skipped); <= 16 when infos is set */
+  int32_t nframes;        /* >= 0 (0: the item is skipped); with infos at most the
+                             stream's statistics chunk: 16..64 frames, as many as
+                             fit 32 MiB of 16-byte per-tile rows (64 at 1920x1080) */
   int32_t reserved;       /* must be 0 */
   cog_step_info *infos;   /* host array of nframes entries, or NULL */
 } cog_tick_item;
@@ -260,8 +269,13 @@ typedef struct {
   int32_t blocks_per_cu;  /* persistent workgroups per compute unit; 0: the occupancy limit;
                              -1: no persistence, one workgroup per schedule unit */
   int32_t dynamic;        /* 0: units dealt round-robin; 1: taken from an atomic counter */
-  int32_t group;          /* 64-pixel tiles per schedule unit, 1..1024 */
+  int32_t group;          /* tiles per schedule unit, 1..1024 */
   int32_t use_graph;      /* 1: replay a captured hipGraph; 0: launch directly */
+  int32_t compact;        /* 1: the class's items that advance by one frame (no
+                             sampling) run in a launch of their own with 256-pixel
+                             tiles whose S1 survivors are compacted into one work
+                             list per wave (as cog_step with tile_px 0); 0: every
+                             item runs in 64-pixel one-pixel-per-lane tiles */
 } cog_schedule;
 
 /* Create a batch on hip_stream (NULL: default stream) for up to max_items
@@ -278,7 +292,10 @@ cog_status cog_batch_tick(cog_batch *b, const cog_tick_item *items, int32_t n);
 
 /* Time candidate schedules on this tick's work (reps ticks each, median)
  * and keep, per class, the current schedule unless a candidate is more than
- * 3 % faster (then the fastest).  Every context's state is restored after each
+ * 3 % faster (then the fastest).  Candidates: one workgroup per schedule
+ * unit, or persistent grids at the occupancy limit and at twice it; units of
+ * 1, 4 or 16 tiles; with and without the compacting launch for one-frame
+ * items (18 in all).  Every context's state is restored after each
  * trial, so the streams are left as they were; the masks of the items are
  * written (with the tick's result) and no infos are filled.  best (may be
  * NULL) receives the schedule kept for the first item's class.  Needs

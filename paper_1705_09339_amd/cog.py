@@ -66,7 +66,7 @@ class cog_tick_item(ct.Structure):
 class cog_schedule(ct.Structure):
     _fields_ = [
         ("blocks_per_cu", ct.c_int32), ("dynamic", ct.c_int32), ("group", ct.c_int32),
-        ("use_graph", ct.c_int32),
+        ("use_graph", ct.c_int32), ("compact", ct.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -418,7 +418,8 @@ def cog_batch_autotune(b: int, entries, reps: int = 3) -> dict:
 
 def cog_batch_set_schedule(b: int, channels: int, K: int, dtype: int, **kw) -> None:
     s = cog_schedule(blocks_per_cu=kw.get("blocks_per_cu", -1), dynamic=kw.get("dynamic", 0),
-                     group=kw.get("group", 4), use_graph=kw.get("use_graph", 1))
+                     group=kw.get("group", 4), use_graph=kw.get("use_graph", 1),
+                     compact=kw.get("compact", 1))
     _check(lib.cog_batch_set_schedule(b, channels, K, dtype, ct.byref(s)))
 
 

@@ -19,7 +19,6 @@ namespace {
 thread_local std::string g_err;
 
 constexpr uint32_t kMagic = 0x31474F43u;  // "COG1"
-using cog_rt::kChunk;
 using cog_rt::Plan;
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
@@ -40,8 +39,7 @@ cog_status hip_fail(cog_ctx *h, hipError_t e, const char *what) {
 }
 
 void fill_infos(const cog_ctx *h, int64_t first_frame, int n, const uint32_t *blocks,
-                cog_step_info *infos) {
-  const int nb = h->plan.nblk;
+                cog_step_info *infos, int nb) {
   for (int f = 0; f < n; ++f) {
     int64_t s[cog::kStat] = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint32_t *row = blocks + (size_t)f * nb * cog::kStat;
@@ -114,6 +112,7 @@ Plan make_plan(const cog_params *p) {
   const bool cascade = p->path == COG_PATH_CASCADE;
   if (cascade) {
     int tile = p->tile_px;
+    pl.auto_tile = tile == 0;
     if (tile == 0) tile = 64;
     pl.tile = tile;
     pl.ppt = tile >= cog::kNT ? tile / cog::kNT : tile / 64;
@@ -145,10 +144,16 @@ Plan make_plan(const cog_params *p) {
   pl.off_kdew = off;
   off += align256(256 * 16 * 2);
   pl.off_partials = off;
-  off += align256((size_t)kChunk * pl.nslots * cog::kStat * 4);
+  const size_t row_bytes = (size_t)pl.nslots * 16;
+  pl.stat_chunk = (int)std::max<size_t>(cog_rt::kChunkMin,
+                                        std::min<size_t>(cog_rt::kChunkMax, cog_rt::kRowBudget / row_bytes));
+  off += align256((size_t)pl.stat_chunk * row_bytes);
   pl.nblk = (pl.nslots + cog::kStatBlock - 1) / cog::kStatBlock;
+  const size_t sum_bytes = (size_t)pl.nblk * cog::kStat * 4;
+  pl.stat_frames = (int)std::max<size_t>((size_t)pl.stat_chunk,
+                                         std::min<size_t>(cog_rt::kSumFramesMax, cog_rt::kSumBudget / sum_bytes));
   pl.off_statout = off;
-  off += align256((size_t)kChunk * pl.nblk * cog::kStat * 4);
+  off += align256((size_t)pl.stat_frames * sum_bytes);
   pl.total = off;
   return pl;
 }
@@ -222,49 +227,106 @@ cog_status ensure_stage(cog_ctx *h, size_t in_bytes, size_t mask_bytes) {
 }
 
 // Runs n frames starting at frames (device) writing masks (device or NULL).
+// With statistics the frames go in launches of at most stat_chunk frames;
+// each launch's rows are reduced on the device into the sums buffer, which
+// is read back (one copy, one synchronisation) when full and at the end.
 cog_status run_frames(cog_ctx *h, const void *dframes, int n, uint8_t *dmasks, bool want_stats,
                       cog_step_info *infos) {
   const Plan &pl = h->plan;
   const int64_t fstride = pl.P * pl.C;  // elements
   const size_t esz = (size_t)pl.sin;
+  uint32_t *sums = reinterpret_cast<uint32_t *>(h->dstate + pl.off_statout);
+  const size_t sum_cap = (size_t)pl.stat_frames * pl.nblk * cog::kStat;  // words
+  struct Pending { int first, cnt, nblk; size_t off; };
+  std::vector<Pending> pend;
+  size_t used = 0;
+  auto flush = [&]() -> cog_status {
+    if (pend.empty()) return COG_OK;
+    h->host_stats.resize(used);
+    hipError_t e = hipMemcpyAsync(h->host_stats.data(), sums, used * 4, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "statistics copy");
+    for (const Pending &q : pend)
+      cog_rt::fill_infos(h, h->frame + q.first, q.cnt, h->host_stats.data() + q.off, infos + q.first,
+                         q.nblk);
+    pend.clear();
+    used = 0;
+    return COG_OK;
+  };
+  // rows of the launches: the state's chunk, or the grown workspace
+  uint4 *rows = reinterpret_cast<uint4 *>(h->dstate + pl.off_partials);
+  int chunk = pl.stat_chunk;
+  if (want_stats && n > pl.stat_chunk) {
+    const size_t row_bytes = (size_t)pl.nslots * 16;
+    const size_t want = std::min((size_t)n * row_bytes, cog_rt::kRowWorkspaceMax / row_bytes * row_bytes);
+    if (want > h->rows_ws_bytes) {
+      uint4 *p = nullptr;
+      if (hipMalloc((void **)&p, want) == hipSuccess) {
+        if (h->rows_ws) {
+          (void)hipStreamSynchronize(h->stream);  // earlier launches may still read the old rows
+          (void)hipFree(h->rows_ws);
+        }
+        h->rows_ws = p;
+        h->rows_ws_bytes = want;
+      } else {
+        (void)hipGetLastError();  // keep the smaller workspace (or the chunk)
+      }
+    }
+    if (h->rows_ws && h->rows_ws_bytes / row_bytes > (size_t)chunk) {
+      rows = h->rows_ws;
+      // (a launch's sums must fit the device sums buffer too)
+      chunk = (int)std::min<size_t>(std::min<size_t>(h->rows_ws_bytes / row_bytes, (size_t)n),
+                                    (size_t)pl.stat_frames);
+    }
+  }
   int done = 0;
   while (done < n) {
-    const int cnt = want_stats ? std::min(kChunk, n - done) : (n - done);
+    const int cnt = want_stats ? std::min(chunk, n - done) : (n - done);
     cog::Frames fr{};
     fr.x = static_cast<const char *>(dframes) + (size_t)done * fstride * esz;
     fr.stride = fstride;
     fr.mask = dmasks ? dmasks + (size_t)done * pl.P : nullptr;
     fr.mstride = pl.P;
-    fr.partials = want_stats ? reinterpret_cast<uint32_t *>(h->dstate + pl.off_partials) : nullptr;
-    fr.nslots = pl.nslots;
+    fr.partials = want_stats ? rows : nullptr;
     fr.nframes = cnt;
     fr.frame0 = h->frame + done;
+    // one frame with the automatic tile choice: the per-frame kernel, whose
+    // 256-pixel tiles compact the survivors (the multi-frame kernel keeps the
+    // dense state in registers across frames instead)
+    const bool cascade = h->p.path == COG_PATH_CASCADE;
+    const bool one = cascade && pl.auto_tile && cnt == 1 && !(h->p.stage_mask & COG_STAGE_SAMPLE);
+    const int nslots = one ? (int)((pl.P + cog::kFrameTile - 1) / cog::kFrameTile) : pl.nslots;
+    fr.nslots = nslots;
     hipError_t e;
-    if (h->p.path == COG_PATH_CASCADE)
+    if (one)
+      e = cog::launch_frame(pl.C, pl.K, h->p.dtype == COG_F32, h->buf, fr, h->kp, h->stream);
+    else if (cascade)
       e = cog::launch_cascade(pl.C, pl.K, h->p.dtype == COG_F32, pl.tile, h->buf, fr, h->kp,
                               h->stream);
     else
       e = cog::launch_gmm(pl.C, pl.K, h->p.dtype == COG_F32, h->buf, fr, h->kp, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "kernel launch");
     if (want_stats) {
-      // per-frame sums on the device, then a small copy
+      // per-frame sums of this launch on the device, beside the earlier ones
+      const int nblk = (nslots + cog::kStatBlock - 1) / cog::kStatBlock;
+      const size_t nw = (size_t)cnt * nblk * cog::kStat;
+      if (used + nw > sum_cap) {
+        cog_status s = flush();
+        if (s != COG_OK) return s;
+      }
       cog::StatJob job{};
       job.partials = fr.partials;
-      job.out = reinterpret_cast<uint32_t *>(h->dstate + pl.off_statout);
-      job.nslots = pl.nslots;
+      job.out = sums + used;
+      job.nslots = nslots;
       job.nframes = cnt;
       e = cog::launch_stats(job, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "statistics launch");
-      const size_t nw = (size_t)cnt * pl.nblk * cog::kStat;
-      h->host_stats.resize(nw);
-      e = hipMemcpyAsync(h->host_stats.data(), job.out, nw * 4, hipMemcpyDeviceToHost, h->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-      if (e != hipSuccess) return hip_fail(h, e, "statistics copy");
-      cog_rt::fill_infos(h, h->frame + done, cnt, h->host_stats.data(), infos + done);
+      pend.push_back(Pending{done, cnt, nblk, used});
+      used += nw;
     }
     done += cnt;
   }
-  return COG_OK;
+  return flush();
 }
 
 // Grouping preconditions shared by both entry points.
@@ -592,6 +654,7 @@ void cog_destroy(cog_ctx *h) {
   if (h->own_state && h->dstate) (void)hipFree(h->dstate);
   if (h->stage_in) (void)hipFree(h->stage_in);
   if (h->stage_mask) (void)hipFree(h->stage_mask);
+  if (h->rows_ws) (void)hipFree(h->rows_ws);
   delete h;
 }
 

@@ -2,7 +2,9 @@
 //
 // A tick groups its items by class (channels, K, input type); each class
 // gets one persistent launch of k_tick over the concatenated 64-pixel tiles
-// of its streams.  The per-item descriptors (frames, state pointers,
+// of its streams -- or, when the class's schedule compacts, its items that
+// advance by one frame get a launch of their own, k_tick_c over 256-pixel
+// tiles whose survivors are compacted per wave.  The per-item descriptors (frames, state pointers,
 // parameters, first tile) are written to pinned host memory and copied to a
 // fixed device region per class position, so a captured hipGraph of the
 // tick's launches stays valid from tick to tick and is replayed whenever the
@@ -12,6 +14,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <set>
 #include <new>
 #include <string>
 #include <tuple>
@@ -24,6 +27,7 @@
 namespace {
 
 constexpr int kMaxClasses = 8;     // classes in one tick
+constexpr int kMaxLaunches = 2 * kMaxClasses;  // a compacting and a plain launch per class
 constexpr int kMaxGraphs = 64;     // cached graph executables
 constexpr int kMaxSeen = 256;      // launch sets remembered for capture on reuse
 constexpr int kMaxItemsLimit = 4096;
@@ -46,6 +50,7 @@ ClassKey class_of(const cog_ctx *h) {
 // One class's launch in a tick.
 struct Launch {
   ClassKey key;
+  bool compact = false;  // k_tick_c over kFrameTile-pixel tiles (one frame per item)
   bool lp = false;
   int grid = 0;
   int dynamic = 0;
@@ -82,7 +87,7 @@ struct cog_batch {
   int ncu = 0;
   int max_items = 0;
   size_t region_bytes = 0;   // head + max_items items
-  char *ddesc = nullptr;     // kMaxClasses regions, then the statistics job table
+  char *ddesc = nullptr;     // kMaxLaunches regions, then the statistics job table
   size_t desc_bytes = 0;
   char *hdesc[2] = {nullptr, nullptr};
   hipEvent_t hev[2] = {nullptr, nullptr};
@@ -119,7 +124,13 @@ cog_schedule default_schedule() {
   s.dynamic = 0;
   s.group = 4;
   s.use_graph = 1;
+  s.compact = 1;
   return s;
+}
+
+// Tiles of one item in a launch.
+int64_t item_tiles(const cog_ctx *h, bool compact) {
+  return compact ? (h->plan.P + cog::kFrameTile - 1) / cog::kFrameTile : h->plan.ntiles;
 }
 
 std::string check_schedule(const cog_schedule *s) {
@@ -128,14 +139,16 @@ std::string check_schedule(const cog_schedule *s) {
   if (s->dynamic != 0 && s->dynamic != 1) return "dynamic must be 0 or 1";
   if (s->group < 1 || s->group > 1024) return "group must be in [1, 1024]";
   if (s->use_graph != 0 && s->use_graph != 1) return "use_graph must be 0 or 1";
+  if (s->compact != 0 && s->compact != 1) return "compact must be 0 or 1";
   return std::string();
 }
 
-int occupancy(cog_batch *b, const ClassKey &k, bool lp) {
-  const auto key = std::make_tuple(k.C, k.K, k.f32, k.samp, lp ? 1 : 0);
+int occupancy(cog_batch *b, const ClassKey &k, bool lp, bool compact) {
+  const auto key = std::make_tuple(k.C, k.K, k.f32, k.samp, compact ? 2 : (lp ? 1 : 0));
   auto it = b->occ.find(key);
   if (it != b->occ.end()) return it->second;
-  int n = cog::tick_blocks_per_cu(k.C, k.K, k.f32 != 0, lp, k.samp != 0);
+  int n = compact ? cog::tick_c_blocks_per_cu(k.C, k.K, k.f32 != 0)
+                  : cog::tick_blocks_per_cu(k.C, k.K, k.f32 != 0, lp, k.samp != 0);
   if (n < 1) n = 1;
   b->occ[key] = n;
   return n;
@@ -151,7 +164,16 @@ cog_status plan_tick(cog_batch *b, const cog_tick_item *items, int32_t n, bool w
   if (n > 0 && !items) return bfail(COG_E_INVALID, "items is NULL");
   std::vector<const cog_ctx *> seen;
   seen.reserve(n);
-  std::map<ClassKey, int> pos;
+  // an item's launch: its class, compacting when the class's schedule says
+  // so and the item advances by one frame without sampling
+  auto compact_of = [&](const cog_tick_item &it) {
+    const ClassKey key = class_of(it.ctx);
+    if (key.samp || it.nframes != 1) return false;
+    auto sit = b->sched.find(key.sched_key());
+    return (sit == b->sched.end() ? default_schedule() : sit->second).compact != 0;
+  };
+  std::map<std::pair<ClassKey, bool>, int> pos;
+  std::map<ClassKey, int> classes;
   for (int i = 0; i < n; ++i) {
     const cog_tick_item &it = items[i];
     cog_ctx *h = it.ctx;
@@ -166,15 +188,17 @@ cog_status plan_tick(cog_batch *b, const cog_tick_item *items, int32_t n, bool w
     if (it.nframes == 0) continue;
     if (!it.frames) return bfail(COG_E_INVALID, "frames is NULL");
     if (want_infos && it.infos) {
-      if (it.nframes > cog_rt::kChunk) return bfail(COG_E_INVALID, "at most 16 frames per item with infos");
+      if (it.nframes > h->plan.stat_chunk)
+        return bfail(COG_E_INVALID, "too many frames for one item with infos (the stream's statistics "
+                                    "workspace holds " + std::to_string(h->plan.stat_chunk) + ")");
       any_infos = true;
     }
     const ClassKey key = class_of(h);
-    auto p = pos.find(key);
-    if (p == pos.end()) {
-      if ((int)pos.size() == kMaxClasses) return bfail(COG_E_INVALID, "more than 8 classes in one tick");
-      pos[key] = -1;
+    if (classes.find(key) == classes.end()) {
+      if ((int)classes.size() == kMaxClasses) return bfail(COG_E_INVALID, "more than 8 classes in one tick");
+      classes[key] = 0;
     }
+    pos[std::make_pair(key, compact_of(it))] = -1;
   }
   std::sort(seen.begin(), seen.end());
   if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
@@ -183,13 +207,16 @@ cog_status plan_tick(cog_batch *b, const cog_tick_item *items, int32_t n, bool w
   int j = 0;
   for (auto &kv : pos) kv.second = j++;
   launches.resize(pos.size());
-  for (auto &kv : pos) launches[kv.second].key = kv.first;
+  for (auto &kv : pos) {
+    launches[kv.second].key = kv.first.first;
+    launches[kv.second].compact = kv.first.second;
+  }
   for (int i = 0; i < n; ++i) {
     if (items[i].nframes == 0) continue;
-    const ClassKey key = class_of(items[i].ctx);
-    Launch &L = launches[pos[key]];
+    const bool c = compact_of(items[i]);
+    Launch &L = launches[pos[std::make_pair(class_of(items[i].ctx), c)]];
     L.items.push_back(i);
-    L.tiles += items[i].ctx->plan.ntiles;
+    L.tiles += item_tiles(items[i].ctx, c);
   }
   for (Launch &L : launches) {
     if (L.tiles > 0x7fffffff) return bfail(COG_E_INVALID, "a tick's class exceeds 2^31 tiles");
@@ -207,7 +234,7 @@ cog_status plan_tick(cog_batch *b, const cog_tick_item *items, int32_t n, bool w
       L.grid = (int)g;
       L.dynamic = 0;
     } else {
-      const int bpc = s.blocks_per_cu == 0 ? occupancy(b, L.key, L.lp) : s.blocks_per_cu;
+      const int bpc = s.blocks_per_cu == 0 ? occupancy(b, L.key, L.lp, L.compact) : s.blocks_per_cu;
       const int64_t cap = (int64_t)bpc * b->ncu;
       L.grid = (int)(units >= cap ? cap : std::min(cap, grid_bucket(units)));
       L.dynamic = s.dynamic;
@@ -227,10 +254,12 @@ cog::TickItem *region_items(cog_batch *b, char *base, int j) {
 cog_status launch_all(cog_batch *b, const std::vector<Launch> &launches) {
   for (size_t j = 0; j < launches.size(); ++j) {
     const Launch &L = launches[j];
-    hipError_t e = cog::launch_tick(L.key.C, L.key.K, L.key.f32 != 0, L.lp, L.key.samp != 0,
-                                    region_head(b, b->ddesc, (int)j),
-                                    region_items(b, b->ddesc, (int)j), L.grid, L.dynamic,
-                                    b->stream);
+    hipError_t e = L.compact
+        ? cog::launch_tick_c(L.key.C, L.key.K, L.key.f32 != 0, region_head(b, b->ddesc, (int)j),
+                             region_items(b, b->ddesc, (int)j), L.grid, L.dynamic, b->stream)
+        : cog::launch_tick(L.key.C, L.key.K, L.key.f32 != 0, L.lp, L.key.samp != 0,
+                           region_head(b, b->ddesc, (int)j), region_items(b, b->ddesc, (int)j),
+                           L.grid, L.dynamic, b->stream);
     if (e != hipSuccess) return bhip(e, "tick launch");
   }
   return COG_OK;
@@ -244,6 +273,7 @@ cog_status run_graph(cog_batch *b, const std::vector<Launch> &launches) {
     key.push_back(L.key.K);
     key.push_back(L.key.f32);
     key.push_back(L.key.samp);
+    key.push_back(L.compact);
     key.push_back(L.lp);
     key.push_back(L.grid);
     key.push_back(L.dynamic);
@@ -303,6 +333,7 @@ cog_status execute(cog_batch *b, const cog_tick_item *items, const std::vector<L
   char *hb = b->hdesc[cur];
   std::vector<cog::StatJob> jobs;
   std::vector<size_t> job_item, job_off;
+  std::vector<int> job_blk;
   size_t stat_words = 0;
   int max_blk = 0, max_fr = 0;
   for (size_t j = 0; j < launches.size(); ++j) {
@@ -325,23 +356,26 @@ cog_status execute(cog_batch *b, const cog_tick_item *items, const std::vector<L
       d.fr.mask = it.masks;
       d.fr.mstride = h->plan.P;
       const bool want = stats && it.infos;
-      d.fr.partials = want ? reinterpret_cast<uint32_t *>(h->dstate + h->plan.off_partials) : nullptr;
-      d.fr.nslots = h->plan.nslots;
+      d.fr.partials = want ? reinterpret_cast<uint4 *>(h->dstate + h->plan.off_partials) : nullptr;
+      const int nslots = (int)item_tiles(h, L.compact);
+      const int nblk = (nslots + cog::kStatBlock - 1) / cog::kStatBlock;
+      d.fr.nslots = nslots;
       d.fr.nframes = it.nframes;
       d.fr.frame0 = h->frame;
       d.b = h->buf;
       d.kp = h->kp;
       d.tile_begin = tb;
-      tb += h->plan.ntiles;
+      tb += nslots;
       if (want) {
         cog::StatJob sj{};
         sj.partials = d.fr.partials;
-        sj.nslots = h->plan.nslots;
+        sj.nslots = nslots;
         sj.nframes = it.nframes;
         job_item.push_back((size_t)L.items[q]);
+        job_blk.push_back(nblk);
         job_off.push_back(stat_words);
-        stat_words += (size_t)it.nframes * h->plan.nblk * cog::kStat;
-        max_blk = std::max(max_blk, h->plan.nblk);
+        stat_words += (size_t)it.nframes * nblk * cog::kStat;
+        max_blk = std::max(max_blk, nblk);
         max_fr = std::max(max_fr, it.nframes);
         jobs.push_back(sj);
       }
@@ -356,7 +390,7 @@ cog_status execute(cog_batch *b, const cog_tick_item *items, const std::vector<L
     b->dstat_cap = stat_words;
   }
   for (size_t q = 0; q < jobs.size(); ++q) jobs[q].out = b->dstat + job_off[q];
-  char *hjobs = hb + (size_t)kMaxClasses * b->region_bytes;
+  char *hjobs = hb + (size_t)kMaxLaunches * b->region_bytes;
   if (!jobs.empty()) std::memcpy(hjobs, jobs.data(), jobs.size() * sizeof(cog::StatJob));
 
   // uploads: the used prefix of each class region, then the job table
@@ -366,7 +400,7 @@ cog_status execute(cog_batch *b, const cog_tick_item *items, const std::vector<L
                                   hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return bhip(e, "descriptor upload");
   }
-  char *djobs = b->ddesc + (size_t)kMaxClasses * b->region_bytes;
+  char *djobs = b->ddesc + (size_t)kMaxLaunches * b->region_bytes;
   if (!jobs.empty()) {
     hipError_t e = hipMemcpyAsync(djobs, hjobs, jobs.size() * sizeof(cog::StatJob),
                                   hipMemcpyHostToDevice, b->stream);
@@ -393,7 +427,8 @@ cog_status execute(cog_batch *b, const cog_tick_item *items, const std::vector<L
     if (e != hipSuccess) return bhip(e, "statistics copy");
     for (size_t q = 0; q < jobs.size(); ++q) {
       const cog_tick_item &it = items[job_item[q]];
-      cog_rt::fill_infos(it.ctx, it.ctx->frame, it.nframes, b->hstat.data() + job_off[q], it.infos);
+      cog_rt::fill_infos(it.ctx, it.ctx->frame, it.nframes, b->hstat.data() + job_off[q], it.infos,
+                         job_blk[q]);
     }
   }
   return COG_OK;
@@ -423,7 +458,7 @@ cog_status cog_batch_create(void *hip_stream, int32_t max_items, cog_batch **out
   b->ncu = ncu;
   b->max_items = max_items;
   b->region_bytes = align256(sizeof(cog::TickHead) + (size_t)max_items * sizeof(cog::TickItem));
-  b->desc_bytes = (size_t)kMaxClasses * b->region_bytes +
+  b->desc_bytes = (size_t)kMaxLaunches * b->region_bytes +
                   align256((size_t)max_items * sizeof(cog::StatJob));
   bool ok = hipMalloc((void **)&b->ddesc, b->desc_bytes) == hipSuccess;
   for (int i = 0; i < 2 && ok; ++i) {
@@ -508,14 +543,22 @@ cog_status cog_batch_autotune(cog_batch *b, const cog_tick_item *items, int32_t 
 
   // candidates: one workgroup per unit, and persistent grids at the
   // occupancy limit and at twice it, units dealt round-robin (the atomic
-  // queue is settable but measured far slower, so it is not tried)
+  // queue is settable but measured far slower, so it is not tried); each
+  // with and without the compacting launch for one-frame items
   std::vector<cog_schedule> cand;
-  for (int bpc : {-1, 0, -2})  // -2: twice the occupancy limit
-    for (int g : {1, 4, 16}) cand.push_back(cog_schedule{bpc, 0, g, 1});
+  for (int c : {1, 0})
+    for (int bpc : {-1, 0, -2})  // -2: twice the occupancy limit
+      for (int g : {1, 4, 16}) cand.push_back(cog_schedule{bpc, 0, g, 1, c});
 
-  for (size_t j = 0; j < launches.size() && s == COG_OK; ++j) {
+  // one tuning pass per class (a class may have a compacting and a plain
+  // launch); the whole tick is timed for every candidate
+  std::vector<size_t> firsts;
+  std::set<ClassKey> tuned;
+  for (size_t j = 0; j < launches.size(); ++j)
+    if (tuned.insert(launches[j].key.sched_key()).second) firsts.push_back(j);
+  for (size_t fi = 0; fi < firsts.size() && s == COG_OK; ++fi) {
+    const size_t j = firsts[fi];
     const ClassKey key = launches[j].key.sched_key();
-    const int occ_lim = occupancy(b, launches[j].key, launches[j].lp);
     float best_ms = 1e30f;
     cog_schedule best_s = default_schedule();
     auto it0 = b->sched.find(key);
@@ -526,7 +569,8 @@ cog_status cog_batch_autotune(cog_batch *b, const cog_tick_item *items, int32_t 
     trial.insert(trial.end(), cand.begin(), cand.end());
     bool first = true;
     for (cog_schedule c : trial) {
-      if (c.blocks_per_cu == -2) c.blocks_per_cu = std::min(64, 2 * occ_lim);
+      if (c.blocks_per_cu == -2)
+        c.blocks_per_cu = std::min(64, 2 * occupancy(b, launches[j].key, launches[j].lp, c.compact != 0));
       b->sched[key] = c;
       std::vector<float> t;
       // one untimed round first (graph capture, cold caches)
@@ -557,7 +601,7 @@ cog_status cog_batch_autotune(cog_batch *b, const cog_tick_item *items, int32_t 
       first = false;
     }
     b->sched[key] = best_s;
-    if (j == 0 && best) *best = best_s;
+    if (fi == 0 && best) *best = best_s;
   }
   // the streams as they were
   if (snap) {

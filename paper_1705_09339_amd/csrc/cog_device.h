@@ -9,11 +9,21 @@ namespace cog {
 constexpr int kNT = 256;        // threads per workgroup (4 wave64)
 constexpr int kNW = kNT / 64;   // waves per workgroup
 constexpr int kBins = 16;       // prior bins per channel
-constexpr int kStat = 8;        // counters per statistics slot:
+constexpr int kStat = 8;        // reduced counters per block and frame:
                                 // n0, n1, n2, n3, n3_bg, n_fg, n_skip, unused
+// A kernel's statistics row per tile and frame: 16-bit counts packed in four
+// words (a tile has at most 1024 pixels).
+__host__ __device__ inline uint4 stat_row(uint32_t n0, uint32_t n1, uint32_t n2, uint32_t n3,
+                                          uint32_t n3bg, uint32_t nfg, uint32_t nskip) {
+  return make_uint4(n0 | (n1 << 16), n2 | (n3 << 16), n3bg | (nfg << 16), nskip);
+}
 
-// Floats per per-pixel mixture record: {w[K], var[K], mu[K][C]} padded to 16 B.
-__host__ __device__ constexpr int rec_floats(int C, int K) { return ((K * (C + 2)) + 3) & ~3; }
+// Floats of one pixel's mixture {w[K], var[K], mu[K][C]}.
+__host__ __device__ constexpr int mix_floats(int C, int K) { return K * (C + 2); }
+// Floats per per-pixel mixture record, padded to 16 B.  (Records padded to
+// whole 128-byte lines were measured slower on the per-frame path: survivors
+// cluster, so adjacent records share lines anyway, and the padding is read.)
+__host__ __device__ constexpr int rec_floats(int C, int K) { return (mix_floats(C, K) + 3) & ~3; }
 // Floats per running-average record {mu_r[C], var_r}.
 __host__ __device__ constexpr int rga_floats(int C) { return C == 3 ? 4 : 2; }
 // Bytes per prior record {t[C][16] u8, a, b, g f32} padded to 32/64 B.
@@ -53,7 +63,7 @@ struct Frames {
   int64_t stride;      // elements between frames
   uint8_t *mask;       // mask of frame 0 or nullptr
   int64_t mstride;     // bytes between masks
-  uint32_t *partials;  // [nframes][nslots][kStat] or nullptr
+  uint4 *partials;     // statistics rows [nframes][nslots] (stat_row) or nullptr
   int nslots;
   int nframes;
   int64_t frame0;      // index of frame 0 in the stream (sampling phase)
@@ -84,7 +94,7 @@ struct TickHead {
 // Per-frame reduction of the per-tile counters of one run of frames:
 // out[f][blk][kStat] = sums over the slots of block blk (kStatBlock slots).
 struct StatJob {
-  const uint32_t *partials;  // [nframes][nslots][kStat]
+  const uint4 *partials;     // rows [nframes][nslots]
   uint32_t *out;             // [nframes][ceil(nslots / kStatBlock)][kStat]
   int32_t nslots;
   int32_t nframes;
@@ -111,11 +121,24 @@ hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, 
                           const KParams &kp, hipStream_t s);
 hipError_t launch_gmm(int C, int K, bool f32in, const Buffers &b, const Frames &fr,
                       const KParams &kp, hipStream_t s);
+// One frame (fr.nframes == 1, no sampling) in 256-pixel tiles with compacted
+// survivors; its statistics rows have ceil(P / kFrameTile) slots.
+#ifndef COG_FRAME_TILE
+#define COG_FRAME_TILE 256
+#endif
+constexpr int kFrameTile = COG_FRAME_TILE;
+hipError_t launch_frame(int C, int K, bool f32in, const Buffers &b, const Frames &fr,
+                        const KParams &kp, hipStream_t s);
 // Persistent tick over one class (C, K, input type) of streams: grid
 // workgroups of one wave; dynamic = 0 deals units round-robin by workgroup,
 // 1 hands them out from head->queue.
 hipError_t launch_tick(int C, int K, bool f32in, bool lp, bool samp, TickHead *head,
                        const TickItem *items, int grid, int dynamic, hipStream_t s);
+// The compacting tick: every item advances by one frame (no sampling) in
+// kFrameTile-pixel tiles; item i owns tiles [tile_begin, + ceil(P / kFrameTile)).
+hipError_t launch_tick_c(int C, int K, bool f32in, TickHead *head, const TickItem *items, int grid,
+                         int dynamic, hipStream_t s);
+int tick_c_blocks_per_cu(int C, int K, bool f32in);
 // Statistics reduction: one job by value, or n jobs from a device table
 // (grid covers max_blocks x max_frames x n).
 hipError_t launch_stats(const StatJob &job, hipStream_t s);
@@ -165,6 +188,14 @@ hipError_t launch_tick_k(int C, bool f32in, bool lp, bool samp, TickHead *head,
                          const TickItem *items, int grid, int dynamic, hipStream_t s);
 template <int K>
 int tick_blocks_per_cu_k(int C, bool f32in, bool lp, bool samp);
+template <int K>
+hipError_t launch_tick_c_k(int C, bool f32in, TickHead *head, const TickItem *items, int grid,
+                           int dynamic, hipStream_t s);
+template <int K>
+int tick_c_blocks_per_cu_k(int C, bool f32in);
+template <int K>
+hipError_t launch_frame_k(int C, bool f32in, const Buffers &b, const Frames &fr, const KParams &kp,
+                          hipStream_t s);
 template <int K>
 hipError_t launch_gmm_k(int C, bool f32in, const Buffers &b, const Frames &fr, const KParams &kp,
                         hipStream_t s);

@@ -217,7 +217,7 @@ __device__ __forceinline__ void mix_step(Mix<C, K> &s, const float (&x)[C], floa
 // mu[K][C]}, 16-byte aligned, so a lone survivor reads one or two lines.
 template <int C, int K>
 __device__ __forceinline__ void rec_load(const float *rec, Mix<C, K> &s) {
-  constexpr int R = rec_floats(C, K);
+  constexpr int R = (mix_floats(C, K) + 3) & ~3;  // the used 16-byte words only
   float r[R];
   const float4 *r4 = reinterpret_cast<const float4 *>(rec);
 #pragma unroll
@@ -237,22 +237,24 @@ __device__ __forceinline__ void rec_load(const float *rec, Mix<C, K> &s) {
   }
 }
 
+// Field i of a record: w[K], var[K], mu[K][C], then zero padding (i is a
+// compile-time index once the callers' loops are unrolled).
+template <int C, int K>
+__device__ __forceinline__ float rec_field(const Mix<C, K> &s, int i) {
+  if (i < K) return s.w[i];
+  if (i < 2 * K) return s.var[i - K];
+  if (i < mix_floats(C, K)) return s.mu[(i - 2 * K) / C][(i - 2 * K) % C];
+  return 0.0f;
+}
+
 template <int C, int K>
 __device__ __forceinline__ void rec_store(float *rec, const Mix<C, K> &s) {
-  constexpr int R = rec_floats(C, K);
-  float r[R];
-#pragma unroll
-  for (int i = 0; i < R; ++i) r[i] = 0.0f;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    r[k] = s.w[k];
-    r[K + k] = s.var[k];
-#pragma unroll
-    for (int c = 0; c < C; ++c) r[2 * K + k * C + c] = s.mu[k][c];
-  }
+  constexpr int R = (mix_floats(C, K) + 3) & ~3;  // up to the last used 16-byte word
   float4 *r4 = reinterpret_cast<float4 *>(rec);
 #pragma unroll
-  for (int i = 0; i < R / 4; ++i) r4[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
+  for (int i = 0; i < R / 4; ++i)
+    r4[i] = make_float4(rec_field(s, 4 * i), rec_field(s, 4 * i + 1), rec_field(s, 4 * i + 2),
+                        rec_field(s, 4 * i + 3));
 }
 
 // Baseline: the same fields in groups of 64 pixels (field-major inside a
@@ -829,11 +831,9 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
     if (tid == 0) {
       if (f > 0) {
         uint32_t *sp = &s_stat[(f - 1) & 1][0];
-        if (fr.partials) {
-          uint32_t *dst = fr.partials + ((int64_t)(f - 1) * fr.nslots + blockIdx.x) * kStat;
-#pragma unroll
-          for (int k = 0; k < kStat; ++k) dst[k] = sp[k];
-        }
+        if (fr.partials)
+          fr.partials[(int64_t)(f - 1) * fr.nslots + blockIdx.x] =
+              stat_row(sp[0], sp[1], sp[2], sp[3], sp[4], sp[5], 0u);
 #pragma unroll
         for (int k = 0; k < kStat; ++k) sp[k] = 0u;
       }
@@ -971,9 +971,9 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
   __syncthreads();
   if (tid == 0 && fr.nframes > 0 && fr.partials) {
     const int f = fr.nframes - 1;
-    uint32_t *dst = fr.partials + ((int64_t)f * fr.nslots + blockIdx.x) * kStat;
-#pragma unroll
-    for (int k = 0; k < kStat; ++k) dst[k] = s_stat[f & 1][k];
+    const uint32_t *sp = &s_stat[f & 1][0];
+    fr.partials[(int64_t)f * fr.nslots + blockIdx.x] =
+        stat_row(sp[0], sp[1], sp[2], sp[3], sp[4], sp[5], 0u);
   }
 
 #pragma unroll
@@ -1244,11 +1244,8 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
         cfg += (uint32_t)__popcll(__ballot(valid[j] && lab[j]));
       }
     }
-    if (fr.partials && lane < kStat) {
-      const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
-                       : lane == 4 ? c3bg : lane == 5 ? cfg : 0u;
-      fr.partials[((int64_t)f * fr.nslots + blockIdx.x) * kStat + lane] = v;
-    }
+    if (fr.partials && lane == 0)
+      fr.partials[(int64_t)f * fr.nslots + blockIdx.x] = stat_row(c0, c1, c2, c3, c3bg, cfg, 0u);
     wave_sync();
   }
 
@@ -1361,8 +1358,8 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
   // statistics word in a frame's row; out-of-range lanes are dropped by the
   // buffer stores' bounds check
   const int moff = valid ? (int)p : 0x7fffffff;
-  const int soff = lane < kStat ? (int)(tile * kStat + lane) * 4 : 0x7fffffff;
-  const int srow = fr.nslots * kStat * 4;  // bytes per statistics row
+  const int soff = lane == 0 ? (int)(tile * 16) : 0x7fffffff;
+  const int srow = fr.nslots * 16;  // bytes per frame of statistics rows
 
   // misalignment of the tile's input run within 4 bytes, frame by frame
   const int in_bytes = F32 ? 4 : 1;
@@ -1384,7 +1381,7 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
         fr.mask ? fr.mask + (int64_t)f0 * fr.mstride : nullptr, (short)0,
         fr.mask ? (int)(uint32_t)((uint64_t)nk * (uint64_t)fr.mstride) : 0, 0x00020000);
     const __amdgpu_buffer_rsrc_t sr = __builtin_amdgcn_make_buffer_rsrc(
-        fr.partials ? fr.partials + (int64_t)f0 * fr.nslots * kStat : nullptr, (short)0,
+        fr.partials ? fr.partials + (int64_t)f0 * fr.nslots : nullptr, (short)0,
         fr.partials ? nk * srow : 0, 0x00020000);
     int mis = (mis0 + f0 * mis_step) & 3;
 
@@ -1520,9 +1517,10 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
           const uint32_t c3bg = (uint32_t)__popcll(__ballot(e3 && !lab));
           const uint32_t cfg = (uint32_t)__popcll(__ballot(valid && lab));
           const uint32_t csk = SAMP ? (uint32_t)__popcll(__ballot(halted && valid)) : 0u;
-          const uint32_t v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? c3
-                           : lane == 4 ? c3bg : lane == 5 ? cfg : lane == 6 ? csk : 0u;
-          __builtin_amdgcn_raw_buffer_store_b32(v, sr, soff, k * srow, 0);
+          const uint4 row = stat_row(c0, c1, c2, c3, c3bg, cfg, csk);
+          typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+          const v4u32 rv = {row.x, row.y, row.z, row.w};
+          __builtin_amdgcn_raw_buffer_store_b128(rv, sr, soff, k * srow, 0);
         }
     };
     for (int k = 0; k < nk; k += 2) {
@@ -1571,6 +1569,336 @@ __global__ __launch_bounds__(64, cascade_min_waves(F32, K, SAMP)) void k_cascade
   // regions) is spread evenly over the chip.  (Contiguous tile runs per XCD
   // share boundary cache lines but concentrate that work; measured slower.)
   cascade_tile<C, K, F32, LP, SAMP>(b, fr, kp, blockIdx.x, threadIdx.x, lds);
+}
+
+// ============================================================================
+// The cascade for one frame per launch (a live camera's cog_step), where the
+// dense state streams from HBM every frame.  One wave per 256 consecutive
+// pixels; lane l owns pixels 4l .. 4l+3 of the tile, so a lane's input,
+// previous value, running average and mask are contiguous and move in wide
+// loads and stores.  S0 and S1 run for every pixel in the owning lane; the
+// tile's S1 survivors are compacted into a wave-level LDS work list (ballot,
+// mbcnt prefix) with what S2 needs, and S2/S3 run over the list one survivor
+// per lane: a pass carries up to 64 survivors of 256 pixels, where
+// one-pixel-per-lane tiles leave most lanes of an S3 pass idle.  The results
+// go back to the owners through LDS for the mask, label and statistics.
+// Pixel arithmetic and order are those of cascade_tile, so the two agree bit
+// for bit.
+constexpr int kFramePx = kFrameTile / 64;  // pixels per lane
+
+template <int C, bool F32>
+struct FrameLds {
+  static constexpr int NXW = F32 ? C : 1;
+  uint16_t li[kFrameTile];           // work list: pixel within the tile
+  uint32_t xw[NXW][kFrameTile];      // the survivor's input (u8: packed bytes)
+  float dl[kFrameTile], dr2[kFrameTile], var[kFrameTile];
+  uint8_t res[kFrameTile];           // per pixel: bit 0 label, bit 1 S2 accept, bit 2 S3
+};
+
+// Bits 4j .. 4j+3 of a 16-bit value spread to every fourth bit (bit k to 4k).
+__device__ __forceinline__ uint64_t spread4(uint64_t v) {
+  v &= 0xffffull;
+  v = (v | (v << 24)) & 0x000000ff000000ffull;
+  v = (v | (v << 12)) & 0x000f000f000f000full;
+  v = (v | (v << 6)) & 0x0303030303030303ull;
+  v = (v | (v << 3)) & 0x1111111111111111ull;
+  return v;
+}
+
+template <int C, int K, bool F32>
+__device__ __forceinline__ void frame_tile(const Buffers &b, const Frames &fr, const KParams &kp,
+                                           int64_t tile, int lane, FrameLds<C, F32> &lds) {
+  constexpr int PX = kFramePx;
+  constexpr int R = rec_floats(C, K);
+  constexpr int RG = rga_floats(C);
+  constexpr int PB = prior_bytes(C);
+  constexpr int NXW = FrameLds<C, F32>::NXW;
+  // input dwords of a lane's PX pixels (u8: PX*C bytes; f32: PX*C floats)
+  constexpr int NDW = F32 ? PX * C : (PX * C) / 4;
+  static_assert(F32 || (PX * C) % 4 == 0, "u8 lanes hold whole dwords");
+
+  const int64_t tile0 = tile * kFrameTile;
+  const int64_t p0 = tile0 + PX * lane;
+  const bool fd_on = (kp.stage_mask & 1u) != 0;
+  const bool rga_on = (kp.stage_mask & 2u) != 0;
+  const bool kde_on = (kp.stage_mask & 4u) != 0;
+  const bool tau_zero = kp.tau_fd == 0.0f;
+  // wide path: the whole tile exists and the caller's frame and mask are
+  // dword-aligned (state arrays are 256-byte aligned)
+  const bool wide = tile0 + kFrameTile <= b.P &&
+                    ((reinterpret_cast<uintptr_t>(fr.x) | reinterpret_cast<uintptr_t>(fr.mask)) & 3) == 0;
+
+  bool valid[PX];
+  float x[PX][C], xp[PX][C], rmu[PX][C], rvar[PX];
+  uint32_t raw[NDW];
+  uint32_t lab4 = 0u;  // the lane's PX label bits (one word holds the labels of 16 lanes)
+#pragma unroll
+  for (int j = 0; j < PX; ++j) valid[j] = p0 + j < b.P;
+  if (wide) {
+    // every load of the dense levels issued at once: one memory round trip
+    const uint32_t *qx = reinterpret_cast<const uint32_t *>(
+        static_cast<const char *>(fr.x) + p0 * C * (F32 ? 4 : 1));
+    const uint32_t *qp = reinterpret_cast<const uint32_t *>(
+        static_cast<const char *>(b.prev) + p0 * C * (F32 ? 4 : 1));
+    uint32_t rp[NDW];
+    float rgv[PX][RG];
+#pragma unroll
+    for (int d = 0; d < NDW; ++d) raw[d] = __builtin_nontemporal_load(qx + d);
+#pragma unroll
+    for (int d = 0; d < NDW; ++d) rp[d] = qp[d];
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+      const float *rg = b.rga + (p0 + j) * RG;
+      if constexpr (RG == 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(rg);
+        rgv[j][0] = v.x;
+        rgv[j][1] = v.y;
+        rgv[j][2] = v.z;
+        rgv[j][3] = v.w;
+      } else {
+        const float2 v = *reinterpret_cast<const float2 *>(rg);
+        rgv[j][0] = v.x;
+        rgv[j][1] = v.y;
+      }
+    }
+    const unsigned long long lw = b.labels[p0 >> 6];
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int e = j * C + c;
+        if constexpr (F32) {
+          x[j][c] = __uint_as_float(raw[e]);
+          xp[j][c] = __uint_as_float(rp[e]);
+        } else {
+          x[j][c] = (float)((raw[e >> 2] >> (8 * (e & 3))) & 0xffu);
+          xp[j][c] = (float)((rp[e >> 2] >> (8 * (e & 3))) & 0xffu);
+        }
+        rmu[j][c] = rgv[j][c];
+      }
+      rvar[j] = rgv[j][RG - 1];
+    }
+    lab4 = (uint32_t)((lw >> (p0 & 63)) & 0xfull);
+  } else {
+#pragma unroll
+    for (int d = 0; d < NDW; ++d) raw[d] = 0u;
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+      rvar[j] = 0.0f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[j][c] = xp[j][c] = rmu[j][c] = 0.0f;
+      if (valid[j]) {
+        load_px<C, F32>(fr.x, p0 + j, x[j]);
+        load_px<C, F32>(b.prev, p0 + j, xp[j]);
+        const float *rg = b.rga + (p0 + j) * RG;
+#pragma unroll
+        for (int c = 0; c < C; ++c) rmu[j][c] = rg[c];
+        rvar[j] = rg[RG - 1];
+      }
+    }
+    if (p0 < b.P) lab4 = (uint32_t)((b.labels[p0 >> 6] >> (p0 & 63)) & 0xfull);
+  }
+
+  // ---- dense levels: S0 (frame difference) and S1 (running average)
+  bool s0[PX], s1[PX], surv[PX];
+  float dr2[PX];
+#pragma unroll
+  for (int j = 0; j < PX; ++j) {
+    bool fd_ok;
+    if (!F32 && tau_zero) {
+      fd_ok = true;
+#pragma unroll
+      for (int c = 0; c < C; ++c) fd_ok = fd_ok && x[j][c] == xp[j][c];
+    } else {
+      float d0 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) d0 = fmaxf(d0, fabsf(x[j][c] - xp[j][c]));
+      fd_ok = d0 <= kp.tau_fd;
+    }
+    float d2 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float d = x[j][c] - rmu[j][c];
+      d2 = d2 + d * d;
+    }
+    dr2[j] = d2;
+    s0[j] = valid[j] && fd_on && fd_ok;
+    s1[j] = valid[j] && !s0[j] && rga_on && d2 <= kp.lam_r2 * rvar[j];
+    surv[j] = valid[j] && !s0[j] && !s1[j];
+    if (s1[j]) lab4 &= ~(1u << j);
+  }
+
+  // ---- the owner's writes that do not depend on S2/S3: previous value, and
+  // the running average of every S1 accept (EMA of mean and variance)
+  if (wide) {
+    uint32_t *qp = reinterpret_cast<uint32_t *>(static_cast<char *>(b.prev) + p0 * C * (F32 ? 4 : 1));
+#pragma unroll
+    for (int d = 0; d < NDW; ++d) qp[d] = raw[d];
+  } else {
+#pragma unroll
+    for (int j = 0; j < PX; ++j)
+      if (valid[j]) store_px<C, F32>(b.prev, p0 + j, x[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < PX; ++j) {
+    if (s1[j]) {
+      float nmu[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) nmu[c] = kp.one_m_alpha_rga * rmu[j][c] + kp.alpha_rga * x[j][c];
+      float sr = 0.0f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float e = x[j][c] - nmu[c];
+        sr = sr + e * e;
+      }
+      const float nv = kp.one_m_alpha_rga * rvar[j] + kp.alpha_rga * sr;
+      const float nvar = F32 ? fmaxf(kp.var_min, nv)
+                             : __int_as_float(max(__float_as_int(kp.var_min), __float_as_int(nv)));
+      float *rg = b.rga + (p0 + j) * RG;
+      if constexpr (RG == 4) *reinterpret_cast<float4 *>(rg) = make_float4(nmu[0], nmu[1], nmu[2], nvar);
+      else *reinterpret_cast<float2 *>(rg) = make_float2(nmu[0], nvar);
+    }
+  }
+
+  // ---- work list of the S1 survivors
+  int nA = 0;
+#pragma unroll
+  for (int j = 0; j < PX; ++j) {
+    const unsigned long long bal = __ballot(surv[j]);
+    if (surv[j]) {
+      const int pos = nA + lane_prefix(bal);
+      lds.li[pos] = (uint16_t)(PX * lane + j);
+      if constexpr (F32) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) lds.xw[c][pos] = __float_as_uint(x[j][c]);
+      } else {
+        uint32_t w = 0u;
+#pragma unroll
+        for (int c = 0; c < C; ++c) w |= (uint32_t)x[j][c] << (8 * c);
+        lds.xw[0][pos] = w;
+      }
+      float dl = 0.0f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[j][c] - xp[j][c]));
+      lds.dl[pos] = dl;
+      lds.dr2[pos] = dr2[j];
+      lds.var[pos] = rvar[j];
+    }
+    nA += (int)__popcll(bal);
+  }
+  wave_sync();
+
+  // ---- S2 and S3 over the list, one survivor per lane
+  for (int r0 = 0; r0 < nA; r0 += 64) {
+    const int i = r0 + lane;
+    if (i < nA) {
+      const int li = lds.li[i];
+      const int64_t p = tile0 + li;
+      float xs[C];
+      if constexpr (F32) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) xs[c] = __uint_as_float(lds.xw[c][i]);
+      } else {
+        const uint32_t w = lds.xw[0][i];
+#pragma unroll
+        for (int c = 0; c < C; ++c) xs[c] = (float)((w >> (8 * c)) & 0xffu);
+      }
+      float *grec = b.gmm + p * R;
+      Mix<C, K> m;
+      rec_load<C, K>(grec, m);  // requested before S2 runs
+      float conf = 0.0f;
+      bool accept = false;
+      if (kde_on) {
+        conf = confidence<C, F32>(b.prior + p * PB, xs, lds.dl[i], lds.dr2[i], lds.var[i], kp);
+        accept = conf >= kp.conf_thr;
+      }
+      uint32_t res;
+      if (accept) {
+        res = 2u;  // S2: background by the scene prior, nothing adapts
+      } else {
+        const float ae = kp.alpha * (1.0f - kp.kappa * conf);
+        int l, mp;
+        mix_step<C, K>(m, xs, ae, kp, l, mp);
+        rec_store<C, K>(grec, m);
+        res = 4u | (l ? 1u : 0u);
+        if (!l) {
+          // background from the mixture: the running average takes the
+          // matched component
+          float sm[C], sv = m.var[0];
+#pragma unroll
+          for (int c = 0; c < C; ++c) sm[c] = m.mu[0][c];
+#pragma unroll
+          for (int kk = 1; kk < K; ++kk) {
+            if (mp == kk) {
+              sv = m.var[kk];
+#pragma unroll
+              for (int c = 0; c < C; ++c) sm[c] = m.mu[kk][c];
+            }
+          }
+          float *rg = b.rga + p * RG;
+          if constexpr (RG == 4) *reinterpret_cast<float4 *>(rg) = make_float4(sm[0], sm[1], sm[2], sv);
+          else *reinterpret_cast<float2 *>(rg) = make_float2(sm[0], sv);
+        }
+      }
+      lds.res[li] = (uint8_t)res;
+    }
+  }
+  wave_sync();
+
+  // ---- results back to the owners: mask, labels, level statistics
+  bool e2[PX], e3[PX];
+#pragma unroll
+  for (int j = 0; j < PX; ++j) {
+    e2[j] = e3[j] = false;
+    if (surv[j]) {
+      const uint32_t r = lds.res[PX * lane + j];
+      e2[j] = (r & 2u) != 0;
+      e3[j] = (r & 4u) != 0;
+      lab4 = (r & 1u) ? (lab4 | (1u << j)) : (lab4 & ~(1u << j));
+    }
+  }
+  if (fr.mask) {
+    if (wide) {
+      uint32_t mw = 0u;
+#pragma unroll
+      for (int j = 0; j < PX; ++j) mw |= ((lab4 >> j) & 1u) ? (0xffu << (8 * j)) : 0u;
+      __builtin_nontemporal_store(mw, reinterpret_cast<uint32_t *>(fr.mask + p0));
+    } else {
+#pragma unroll
+      for (int j = 0; j < PX; ++j)
+        if (valid[j]) fr.mask[p0 + j] = ((lab4 >> j) & 1u) ? 255 : 0;
+    }
+  }
+  // label words: word q holds lanes 16q .. 16q+15, four bits each
+  unsigned long long bal[PX];
+#pragma unroll
+  for (int j = 0; j < PX; ++j) bal[j] = __ballot(valid[j] && ((lab4 >> j) & 1u));
+  if (lane < PX && tile0 + 64 * lane < b.P) {
+    const int sh = 16 * lane;
+    uint64_t word = 0ull;
+#pragma unroll
+    for (int j = 0; j < PX; ++j) word |= spread4(bal[j] >> sh) << j;
+    b.labels[(tile0 >> 6) + lane] = word;
+  }
+  if (fr.partials) {
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c3bg = 0, cfg = 0;
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+      c0 += (uint32_t)__popcll(__ballot(s0[j]));
+      c1 += (uint32_t)__popcll(__ballot(s1[j]));
+      c2 += (uint32_t)__popcll(__ballot(e2[j]));
+      c3 += (uint32_t)__popcll(__ballot(e3[j]));
+      c3bg += (uint32_t)__popcll(__ballot(e3[j] && !((lab4 >> j) & 1u)));
+      cfg += (uint32_t)__popcll(bal[j]);
+    }
+    if (lane == 0) fr.partials[tile] = stat_row(c0, c1, c2, c3, c3bg, cfg, 0u);
+  }
+}
+
+template <int C, int K, bool F32>
+__global__ __launch_bounds__(64) void k_frame(Buffers b, Frames fr, KParams kp) {
+  __shared__ FrameLds<C, F32> lds;
+  frame_tile<C, K, F32>(b, fr, kp, blockIdx.x, threadIdx.x, lds);
 }
 
 // ============================================================================
@@ -1634,6 +1962,36 @@ __global__ __launch_bounds__(64, cascade_min_waves(F32, K, SAMP)) void k_tick(Ti
   }
 }
 
+// The batched tick's compacting variant: every item of the launch advances by
+// exactly one frame (no sampling), in the per-frame kernel's 256-pixel tiles
+// (frame_tile), numbered over the items as in k_tick.
+template <int C, int K, bool F32>
+__global__ __launch_bounds__(64) void k_tick_c(TickHead *head, const TickItem *items, int dynamic) {
+  __shared__ FrameLds<C, F32> lds;
+  const int lane = threadIdx.x;
+  CTickHead *ch = (CTickHead *)head;
+  CTickItem *ci = (CTickItem *)items;
+  const int total = (int)ch->total_tiles;
+  const int group = ch->group;
+  const int units = (total + group - 1) / group;
+  uint32_t *queue = &head->queue;
+  int u = dynamic ? take_unit(queue, lane) : (int)blockIdx.x;
+  int it = 0;
+  while (u < units) {
+    const int nxt = dynamic ? take_unit(queue, lane) : u + (int)gridDim.x;
+    const int t1 = u < units - 1 ? (u + 1) * group : total;
+    for (int t = u * group; t < t1; ++t) {
+      while (it + 1 < ch->n_items && (int)ci[it + 1].tile_begin <= t) ++it;
+      const Frames fr = const_copy(&items[it].fr);
+      const Buffers b = const_copy(&items[it].b);
+      const KParams kp = const_copy(&items[it].kp);
+      frame_tile<C, K, F32>(b, fr, kp, t - (int)ci[it].tile_begin, lane, lds);
+      wave_sync();  // the next tile reuses the work list
+    }
+    u = nxt;
+  }
+}
+
 // ============================================================================
 // Plain Stauffer-Grimson baseline: every pixel runs the mixture step every
 // frame (alpha fixed), one wave per 64 pixels and one pixel per lane, the
@@ -1678,10 +2036,7 @@ __global__ __launch_bounds__(64) void k_gmm(Buffers b, Frames fr, KParams kp) {
       if (fr.partials) {
         const uint32_t nv = (uint32_t)__popcll(__ballot(valid));
         const uint32_t nf = (uint32_t)__popcll(__ballot(valid && lab));
-        if (lane < kStat) {
-          const uint32_t v = lane == 3 ? nv : lane == 4 ? nv - nf : lane == 5 ? nf : 0u;
-          fr.partials[((int64_t)f * fr.nslots + tile) * kStat + lane] = v;
-        }
+        if (lane == 0) fr.partials[(int64_t)f * fr.nslots + tile] = stat_row(0u, 0u, 0u, nv, nv - nf, nf, 0u);
       }
     }
     wave_sync();
@@ -1766,6 +2121,18 @@ hipError_t launch_cascade_k(int C, bool f32in, int tile, const Buffers &b, const
 }
 
 template <int K>
+hipError_t launch_frame_k(int C, bool f32in, const Buffers &b, const Frames &fr, const KParams &kp,
+                          hipStream_t s) {
+  if (fr.nframes != 1 || (kp.stage_mask & 8u)) return hipErrorInvalidValue;
+  const unsigned g = grid_for(b.P, kFrameTile);
+#define COG_FRAME(CC, FF, _) \
+  hipLaunchKernelGGL((k_frame<CC, K, FF>), dim3(g), dim3(64), 0, s, b, fr, kp)
+  COG_C_CASES(COG_FRAME, 0)
+#undef COG_FRAME
+  return hipGetLastError();
+}
+
+template <int K>
 hipError_t launch_tick_k(int C, bool f32in, bool lp, bool samp, TickHead *head,
                          const TickItem *items, int grid, int dynamic, hipStream_t s) {
   if (grid <= 0) return hipErrorInvalidValue;
@@ -1783,6 +2150,28 @@ hipError_t launch_tick_k(int C, bool f32in, bool lp, bool samp, TickHead *head,
 #undef COG_TICK_LP
 #undef COG_TICK
   return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_tick_c_k(int C, bool f32in, TickHead *head, const TickItem *items, int grid,
+                           int dynamic, hipStream_t s) {
+  if (grid <= 0) return hipErrorInvalidValue;
+#define COG_TICKC(CC, FF, _) \
+  hipLaunchKernelGGL((k_tick_c<CC, K, FF>), dim3(grid), dim3(64), 0, s, head, items, dynamic)
+  COG_C_CASES(COG_TICKC, 0)
+#undef COG_TICKC
+  return hipGetLastError();
+}
+
+template <int K>
+int tick_c_blocks_per_cu_k(int C, bool f32in) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (C == 3 && !f32in) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tick_c<3, K, false>, 64, 0);
+  else if (C == 3 && f32in) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tick_c<3, K, true>, 64, 0);
+  else if (C == 1 && !f32in) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tick_c<1, K, false>, 64, 0);
+  else if (C == 1 && f32in) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tick_c<1, K, true>, 64, 0);
+  return e == hipSuccess ? nb : 0;
 }
 
 template <int K>
@@ -1827,9 +2216,14 @@ hipError_t launch_gmm_k(int C, bool f32in, const Buffers &b, const Frames &fr, c
                                          int64_t, int, const KParams &, hipStream_t);          \
   template hipError_t launch_cascade_k<KK>(int, bool, int, const Buffers &, const Frames &,   \
                                            const KParams &, hipStream_t);                      \
+  template hipError_t launch_frame_k<KK>(int, bool, const Buffers &, const Frames &,           \
+                                         const KParams &, hipStream_t);                        \
   template hipError_t launch_tick_k<KK>(int, bool, bool, bool, TickHead *, const TickItem *,   \
                                         int, int, hipStream_t);                                \
   template int tick_blocks_per_cu_k<KK>(int, bool, bool, bool);                                \
+  template hipError_t launch_tick_c_k<KK>(int, bool, TickHead *, const TickItem *, int, int,   \
+                                          hipStream_t);                                        \
+  template int tick_c_blocks_per_cu_k<KK>(int, bool);                                          \
   template hipError_t launch_gmm_k<KK>(int, bool, const Buffers &, const Frames &,             \
                                        const KParams &, hipStream_t);
 

@@ -20,11 +20,13 @@ __device__ __forceinline__ void stats_block(const StatJob &j, int blk, int f) {
   uint32_t acc[kStat];
 #pragma unroll
   for (int k = 0; k < kStat; ++k) acc[k] = 0u;
-  const uint4 *row = reinterpret_cast<const uint4 *>(j.partials + (int64_t)f * j.nslots * kStat);
+  const uint4 *row = j.partials + (int64_t)f * j.nslots;
   for (int64_t i = s0 + tid; i < s1; i += kNT) {
-    const uint4 a = row[2 * i], c = row[2 * i + 1];
-    acc[0] += a.x; acc[1] += a.y; acc[2] += a.z; acc[3] += a.w;
-    acc[4] += c.x; acc[5] += c.y; acc[6] += c.z; acc[7] += c.w;
+    const uint4 a = row[i];
+    acc[0] += a.x & 0xffffu; acc[1] += a.x >> 16;
+    acc[2] += a.y & 0xffffu; acc[3] += a.y >> 16;
+    acc[4] += a.z & 0xffffu; acc[5] += a.z >> 16;
+    acc[6] += a.w;
   }
 #pragma unroll
   for (int k = 0; k < kStat; ++k) {
@@ -281,11 +283,34 @@ hipError_t launch_tick(int C, int K, bool f32in, bool lp, bool samp, TickHead *h
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_tick_c(int C, int K, bool f32in, TickHead *head, const TickItem *items, int grid,
+                         int dynamic, hipStream_t s) {
+#define CALL(KK) launch_tick_c_k<KK>(C, f32in, head, items, grid, dynamic, s)
+  COG_K_DISPATCH(CALL)
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+int tick_c_blocks_per_cu(int C, int K, bool f32in) {
+#define CALL(KK) tick_c_blocks_per_cu_k<KK>(C, f32in)
+  COG_K_DISPATCH(CALL)
+#undef CALL
+  return 0;
+}
+
 int tick_blocks_per_cu(int C, int K, bool f32in, bool lp, bool samp) {
 #define CALL(KK) tick_blocks_per_cu_k<KK>(C, f32in, lp, samp)
   COG_K_DISPATCH(CALL)
 #undef CALL
   return 0;
+}
+
+hipError_t launch_frame(int C, int K, bool f32in, const Buffers &b, const Frames &fr,
+                        const KParams &kp, hipStream_t s) {
+#define CALL(KK) launch_frame_k<KK>(C, f32in, b, fr, kp, s)
+  COG_K_DISPATCH(CALL)
+#undef CALL
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gmm(int C, int K, bool f32in, const Buffers &b, const Frames &fr,

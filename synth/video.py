@@ -178,6 +178,11 @@ class _Scene:
             return 0.0, W - o.w, 0.0, H - o.h
         return o.w, W - o.w, o.h, H - o.h
 
+    def snapshot(self):
+        """Copies of the objects at the current frame (render() of a frame
+        reads nothing else that advance() changes)."""
+        return [dataclasses.replace(o) for o in self.objs]
+
     def advance(self):
         """Move every object by one frame."""
         vmax = self.spec.rw_vmax
@@ -204,8 +209,11 @@ class _Scene:
                 o.y = min(max(o.y, y0), y1)
         self.t += 1
 
-    def render(self, t: int) -> Tuple[np.ndarray, np.ndarray]:
+    def render(self, t: int, objs=None) -> Tuple[np.ndarray, np.ndarray]:
+        """Frame t with the objects where they are now (or at `objs`, a
+        snapshot taken by `snapshot()` when the scene was at frame t)."""
         spec = self.spec
+        objs = self.objs if objs is None else objs
         W, H = spec.width, spec.height
         img = self.bg.copy()
         lvl = np.float32(0.0)
@@ -217,7 +225,7 @@ class _Scene:
             f = np.float32((1.0 + math.sin(2.0 * math.pi * t / period)) / 2.0)
             img[y0:y0 + side, x0:x0 + side] = ca + (cb - ca) * f + lvl
         gt = np.zeros((H, W), dtype=bool)
-        for o in self.objs:
+        for o in objs:
             if o.kind == "rect":
                 xa, ya = int(round(o.x)), int(round(o.y))
                 xb, yb = min(W, xa + int(o.w)), min(H, ya + int(o.h))
@@ -227,8 +235,11 @@ class _Scene:
             else:
                 xa, xb = max(0, int(math.floor(o.x - o.w))), min(W, int(math.ceil(o.x + o.w)) + 1)
                 ya, yb = max(0, int(math.floor(o.y - o.h))), min(H, int(math.ceil(o.y + o.h)) + 1)
-                yy, xx = np.mgrid[ya:yb, xa:xb]
-                inside = ((xx + 0.5 - o.x) / o.w) ** 2 + ((yy + 0.5 - o.y) / o.h) ** 2 <= 1.0
+                # the same float64 terms as over a full coordinate grid, formed
+                # once per column and per row and summed by broadcasting
+                ex = ((np.arange(xa, xb) + 0.5 - o.x) / o.w) ** 2
+                ey = ((np.arange(ya, yb) + 0.5 - o.y) / o.h) ** 2
+                inside = ex[None, :] + ey[:, None] <= 1.0
                 sub = img[ya:yb, xa:xb]
                 sub[inside] = o.color + lvl
                 gt[ya:yb, xa:xb] |= inside
@@ -252,16 +263,39 @@ def iter_frames(spec: StreamSpec, start: int = 0, stop: Optional[int] = None
 
 
 def make_stream(spec: StreamSpec, start: int = 0, stop: Optional[int] = None,
-                with_gt: bool = False):
-    """Frames [start, stop) as one u8 array [n, H, W, 3] (and GT masks [n, H, W])."""
+                with_gt: bool = False, threads: int = 1):
+    """Frames [start, stop) as one u8 array [n, H, W, 3] (and GT masks [n, H, W]).
+
+    With threads > 1 the object motion is stepped through first (it is
+    sequential and cheap) and the frames are drawn by a thread pool; every
+    frame's noise has its own generator, so the result is the same array."""
     stop = spec.frames if stop is None else stop
     n = stop - start
     frames = np.empty((n, spec.height, spec.width, 3), dtype=np.uint8)
     gts = np.empty((n, spec.height, spec.width), dtype=bool) if with_gt else None
-    for t, f, g in iter_frames(spec, start, stop):
+    if threads <= 1:
+        for t, f, g in iter_frames(spec, start, stop):
+            frames[t - start] = f
+            if with_gt:
+                gts[t - start] = g
+        return (frames, gts) if with_gt else frames
+    from concurrent.futures import ThreadPoolExecutor
+
+    sc = _Scene(spec)
+    snaps = {}
+    for t in range(stop):
+        if t >= start:
+            snaps[t] = sc.snapshot()
+        sc.advance()
+
+    def draw(t):
+        f, g = sc.render(t, snaps.pop(t))
         frames[t - start] = f
         if with_gt:
             gts[t - start] = g
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(draw, range(start, stop)))
     return (frames, gts) if with_gt else frames
 
 

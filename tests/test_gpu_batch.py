@@ -165,10 +165,43 @@ def reference(C, S):
     return streams, plan, run_alone(C, S, streams, plan)
 
 
-def test_batch_equals_alone_default_schedule(C, S, reference):
-    streams, plan, alone = reference
+@pytest.fixture(scope="module")
+def batched_default(C, S, reference):
+    streams, plan, _ = reference
     say("batched, default schedule")
-    assert_same(streams, alone, run_batched(C, S, streams, plan))
+    return run_batched(C, S, streams, plan)
+
+
+def test_batch_equals_alone_default_schedule(C, S, reference, batched_default):
+    streams, plan, alone = reference
+    assert_same(streams, alone, batched_default)
+
+
+def assert_matches_oracle(streams, plan, got, used):
+    """Every stream's batched masks, the per-frame statistics of the ticks
+    that asked for them, and its final state against the oracle run over the
+    same frames."""
+    for i, ((name, p, fr, n_train, _), (mg, infos, blob)) in enumerate(zip(streams, got)):
+        n = used[i]
+        say("oracle check", name, "frames", n)
+        mo, io, so = run_orc(orc_params_like(p), fr[:n_train + n], n_train)
+        compare_masks(mg[:n], mo)
+        assert np.array_equal(mg[:n], mo), (name, int((mg[:n] != mo).sum()))
+        for t, inf in infos.items():
+            off, k = plan[t][i]
+            assert len(inf) == k, (name, t)
+            for a, b in zip(inf, io[off:off + k]):
+                assert dict(a) == dict(b), (name, t, a, b)
+        assert compare_state(canon.parse(blob), so) == 0, name
+
+
+def test_batched_streams_match_oracle(C, reference, batched_default):
+    """Every stream of the batch -- RGB K=5 and K=3, a ragged 33x17 and a
+    sub-tile 7x3 stream, single-channel u8 with K=2 and the f32 latent map --
+    against the oracle directly."""
+    streams, plan, _ = reference
+    used = [sum(row[i][1] for row in plan) for i in range(len(streams))]
+    assert_matches_oracle(streams, plan, batched_default, used)
 
 
 def test_alone_run_matches_oracle(C, reference):
@@ -185,17 +218,18 @@ def test_alone_run_matches_oracle(C, reference):
 
 
 SCHEDULES = [
-    dict(blocks_per_cu=-1, dynamic=0, group=1, use_graph=1),
-    dict(blocks_per_cu=-1, dynamic=0, group=4, use_graph=0),
-    dict(blocks_per_cu=0, dynamic=0, group=1, use_graph=0),
-    dict(blocks_per_cu=0, dynamic=1, group=1, use_graph=1),
-    dict(blocks_per_cu=0, dynamic=1, group=16, use_graph=1),
-    dict(blocks_per_cu=1, dynamic=0, group=3, use_graph=1),
-    dict(blocks_per_cu=1, dynamic=1, group=2, use_graph=0),
+    dict(blocks_per_cu=-1, dynamic=0, group=1, use_graph=1, compact=1),
+    dict(blocks_per_cu=-1, dynamic=0, group=4, use_graph=0, compact=0),
+    dict(blocks_per_cu=0, dynamic=0, group=1, use_graph=0, compact=1),
+    dict(blocks_per_cu=0, dynamic=1, group=1, use_graph=1, compact=0),
+    dict(blocks_per_cu=0, dynamic=1, group=16, use_graph=1, compact=1),
+    dict(blocks_per_cu=1, dynamic=0, group=3, use_graph=1, compact=0),
+    dict(blocks_per_cu=1, dynamic=1, group=2, use_graph=0, compact=1),
+    dict(blocks_per_cu=-1, dynamic=0, group=4, use_graph=1, compact=0),
 ]
 
 
-@pytest.mark.parametrize("sch", SCHEDULES, ids=lambda s: "bpc{blocks_per_cu}-d{dynamic}-g{group}-gr{use_graph}".format(**s))
+@pytest.mark.parametrize("sch", SCHEDULES, ids=lambda s: "bpc{blocks_per_cu}-d{dynamic}-g{group}-gr{use_graph}-c{compact}".format(**s))
 def test_batch_equals_alone_every_schedule(C, S, reference, sch):
     streams, plan, alone = reference
     classes = {(p.channels, p.K, p.dtype) for _, p, *_ in streams}
@@ -266,7 +300,7 @@ def test_batch_errors(C, S):
         with pytest.raises(C.CogError) as e:
             b.tick([(t.h, fr[20:21], None, 1, False)])
         assert e.value.status == C.COG_E_UNSUPPORTED
-        # statistics for more than 64 frames in one item
+        # statistics for more frames than the stream's statistics chunk (64 here)
         big = torch.zeros((70, 16 * 8 * 3), dtype=torch.uint8, device="cuda")
         with pytest.raises(C.CogError) as e:
             b.tick([(a.h, big, None, 70, True)])
@@ -281,8 +315,11 @@ def test_batch_errors(C, S):
             b.set_schedule(3, 3, 0, group=0)
         with pytest.raises(C.CogError):
             b.set_schedule(3, 9, 0)
-        b.set_schedule(3, 3, 0, blocks_per_cu=2, dynamic=1, group=8, use_graph=0)
-        assert b.get_schedule(3, 3, 0) == dict(blocks_per_cu=2, dynamic=1, group=8, use_graph=0)
+        with pytest.raises(C.CogError):
+            b.set_schedule(3, 3, 0, compact=2)
+        b.set_schedule(3, 3, 0, blocks_per_cu=2, dynamic=1, group=8, use_graph=0, compact=0)
+        assert b.get_schedule(3, 3, 0) == dict(blocks_per_cu=2, dynamic=1, group=8, use_graph=0,
+                                               compact=0)
         S.synchronize()
         for c in (a, o, g, t):
             c.close()
@@ -328,3 +365,4 @@ def test_batch_equals_alone_full_size_streams(C, S):
     alone = run_alone(C, S, streams, plan)
     batched = run_batched(C, S, streams, plan)
     assert_same(streams, alone, batched)
+    assert_matches_oracle(streams, plan, batched, used)

@@ -39,10 +39,11 @@ def parity(C, p, fr, n_train, mode="frames"):
     return io
 
 
+@pytest.mark.parametrize("mode", [6, "step"], ids=["runs-of-6", "per-frame"])
 @pytest.mark.parametrize("mask", [1, 2, 4, 3, 5, 6])
-def test_stage_subsets(C, mask):
+def test_stage_subsets(C, mask, mode):
     fr = stream(48, 32, 80, 20, seed_off=mask)
-    io = parity(C, gpu_params(C, 48, 32, K=3, stage_mask=mask), fr, 20, mode=6)
+    io = parity(C, gpu_params(C, 48, 32, K=3, stage_mask=mask), fr, 20, mode=mode)
     tot = {k: sum(i[k] for i in io) for k in ("n0", "n1", "n2")}
     if not mask & 1:
         assert tot["n0"] == 0
@@ -53,7 +54,7 @@ def test_stage_subsets(C, mask):
 
 
 @pytest.mark.parametrize("w,h", [(1, 1), (1, 7), (7, 1), (64, 1), (65, 1), (1, 65), (3, 43)])
-@pytest.mark.parametrize("variant", ["cascade", "sampling", "gmm"])
+@pytest.mark.parametrize("variant", ["cascade", "cascade-per-frame", "sampling", "gmm"])
 def test_tiny_and_thin_frames(C, w, h, variant):
     fr = stream(w, h, 60, 12, seed_off=w * 100 + h)
     kw = {}
@@ -66,7 +67,7 @@ def test_tiny_and_thin_frames(C, w, h, variant):
         assert np.array_equal(mg, mo)
         assert compare_state(sg, so, keys=("gmm", "label", "prev")) == 0
         return
-    parity(C, gpu_params(C, w, h, K=4, **kw), fr, 12, mode=5)
+    parity(C, gpu_params(C, w, h, K=4, **kw), fr, 12, mode="step" if variant == "cascade-per-frame" else 5)
 
 
 @pytest.mark.parametrize("kw", [
@@ -79,12 +80,13 @@ def test_tiny_and_thin_frames(C, w, h, variant):
     dict(lam=100.0, K=1),                  # one component that always matches
     dict(var_min=0.5, var_init=0.5),       # floor equal to the initial variance
 ])
-def test_parameter_extremes(C, kw):
+@pytest.mark.parametrize("mode", [9, "step"], ids=["runs-of-9", "per-frame"])
+def test_parameter_extremes(C, kw, mode):
     kw = dict(kw)
     K = kw.pop("K", 3)
     fr = stream(40, 24, 70, 20, seed_off=len(str(kw)))
-    say("extreme", kw)
-    parity(C, gpu_params(C, 40, 24, K=K, **kw), fr, 20, mode=9)
+    say("extreme", kw, mode)
+    parity(C, gpu_params(C, 40, 24, K=K, **kw), fr, 20, mode=mode)
 
 
 def test_subnormal_weights_long_run(C):

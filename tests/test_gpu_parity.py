@@ -125,11 +125,12 @@ def test_f32_latent_input(C):
     p = gpu_params(C, W, H, c=1, K=3, dtype=C.COG_F32, in_lo=-4.0, in_hi=4.0,
                    var_init=0.25, var_min=0.0025, res_e1=0.2, res_e2=0.6, tau_fd=0.0)
     say("f32 latent", fr.shape)
-    mg, ig, sg = run_gpu(C, p, fr, N, mode="frames")
     mo, io, so = run_orc(orc_params_like(p), fr, N)
-    assert np.array_equal(mg, mo)
-    compare_infos(ig, io)
-    assert compare_state(sg, so) == 0
+    for mode in ("frames", "step"):
+        mg, ig, sg = run_gpu(C, p, fr, N, mode=mode)
+        assert np.array_equal(mg, mo), mode
+        compare_infos(ig, io)
+        assert compare_state(sg, so) == 0, mode
 
 
 # ------------------------------------------------------------------ baseline and identity
@@ -144,6 +145,25 @@ def test_plain_gmm_path_parity(C):
     assert compare_state(sg, so, keys=("gmm", "label", "prev")) == 0
     for i, m in zip(ig, mg):
         assert i["n3"] == 19200 and i["n_fg"] == int((m == 255).sum())
+
+
+def test_plain_gmm_path_parity_640x480_full_frame(C):
+    """The baseline mixture kernel (its own 64-pixel field-major layout) on a
+    full 640x480 stream, every pixel against the oracle, in one launch and
+    frame by frame."""
+    spec = synth.preset("surveil-640x480-k5")
+    N = spec.n_train
+    fr = synth.make_stream(spec, 0, N + 60, threads=16)
+    p = gpu_params(C, 640, 480, K=5, path=C.COG_PATH_GMM)
+    say("plain GMM path 640x480, 60 steps")
+    mo, _, so = run_orc(orc_params_like(p), fr, N, mode="gmm")
+    for mode in ("frames", "step"):
+        mg, ig, sg = run_gpu(C, p, fr, N, mode=mode, infos=mode == "frames")
+        assert np.array_equal(mg, mo), mode
+        assert compare_state(sg, so, keys=("gmm", "label", "prev")) == 0
+        if mode == "frames":
+            for i, m in zip(ig, mg):
+                assert i["n3"] == 640 * 480 and i["n_fg"] == int((m == 255).sum())
 
 
 def test_forced_on_identity_cascade_equals_plain_gmm(C):
@@ -181,11 +201,16 @@ def _sample_pixels(H, W, seed):
 
 
 @pytest.mark.parametrize("name,n_steps", [("surveil-640x480-k5", 60),
-                                          ("surveil-1920x1080-k5-occ30", 12)])
+                                          ("surveil-1920x1080-k5-occ01", 100),
+                                          ("surveil-1920x1080-k5-occ05", 120),
+                                          ("surveil-1920x1080-k5-occ10", 100),
+                                          ("surveil-1920x1080-k5-occ30", 100)])
 def test_full_size_sampled_parity(C, name, n_steps):
+    """The full-size streams through one multi-frame launch (the regime the
+    benchmark times) against the oracle on sampled pixels' time series."""
     spec = synth.preset(name)
     N = spec.n_train
-    fr = synth.make_stream(spec, 0, N + n_steps)
+    fr = synth.make_stream(spec, 0, N + n_steps, threads=16)
     p = gpu_params(C, spec.width, spec.height, K=spec.K)
     say("full size", name, "steps", n_steps)
     mg, ig, sg = run_gpu(C, p, fr, N, mode="frames")
@@ -207,6 +232,37 @@ def test_full_size_sampled_parity(C, name, n_steps):
     compare_masks(mg[:, pix], mo)
     assert np.array_equal(mg[:, pix], mo)
     assert compare_state(sg, so, pix=pix) == 0
+
+
+@pytest.mark.parametrize("name,n_steps", [("surveil-1920x1080-k5-occ05", 30),
+                                          ("surveil-1920x1080-k5-occ30", 30)])
+def test_full_size_per_frame_sampled_parity(C, name, n_steps):
+    """The live-camera regime at 1920x1080: one cog_step per frame (the
+    per-frame kernel with compacted survivors), the per-frame statistics
+    checked on the whole frame and the sampled pixels against the oracle."""
+    spec = synth.preset(name)
+    N = spec.n_train
+    fr = synth.make_stream(spec, 0, N + n_steps, threads=16)
+    p = gpu_params(C, spec.width, spec.height, K=spec.K)
+    say("full size per frame", name, "steps", n_steps)
+    mg, ig, sg = run_gpu(C, p, fr, N, mode="step")
+    P = spec.pixels
+    for i, m in zip(ig, mg):
+        assert i["n0"] + i["n1"] + i["n2"] + i["n3"] == P
+        assert i["n_fg"] == int((m == 255).sum())
+    pix = _sample_pixels(spec.height, spec.width, spec.seed)
+    sub = fr.reshape(len(fr), P, 3)[:, pix][:, None]
+    po = orc_params_like(p)
+    po.width, po.height = len(pix), 1
+    mo, _, so = run_orc(po, sub, N)
+    assert np.array_equal(mg[:, pix], mo)
+    assert compare_state(sg, so, pix=pix) == 0
+    # the same frames through one multi-frame launch give the same result
+    mf, i_f, sf = run_gpu(C, p, fr, N, mode="frames")
+    assert np.array_equal(mf, mg)
+    compare_infos(i_f, ig)
+    for k in ("gmm", "rga", "label", "prev"):
+        assert np.array_equal(sf[k], sg[k]), k
 
 
 # ------------------------------------------------------------------ boundary behaviour

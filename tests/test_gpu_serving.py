@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import gpu_params, say
+from tests import canon
+from tests.gpu_util import compare_masks, compare_state, gpu_params, orc_params_like, run_orc, say
 
 pytestmark = pytest.mark.gpu
 
@@ -119,6 +120,11 @@ def test_serving_mix_equals_alone(C):
         mg = masks[i].cpu().numpy()
         assert np.array_equal(mg, ref[i][0]), (name, int((mg != ref[i][0]).sum()))
         assert states[i] == ref[i][1], (name, "state differs")
+        # and each served stream against the oracle directly
+        mo, _, so = run_orc(orc_params_like(p), fr, 20)
+        compare_masks(mg, mo)
+        assert np.array_equal(mg, mo), (name, int((mg != mo).sum()))
+        assert compare_state(canon.parse(states[i]), so) == 0, name
 
 
 def test_admission_by_budget_and_pool_reuse(C):
@@ -271,5 +277,75 @@ def test_serving_full_size_streams_equal_alone(C):
         srv.close_stream(ids[i])
     srv.close()
     for i in range(2):
-        assert np.array_equal(masks[i].cpu().numpy(), ref[i][0]), i
+        mg = masks[i].cpu().numpy()
+        assert np.array_equal(mg, ref[i][0]), i
         assert states[i] == ref[i][1], i
+        p, fr = streams[i]
+        say("served full-size stream against the oracle", p.width, p.height)
+        mo, _, so = run_orc(orc_params_like(p), fr, 20)
+        compare_masks(mg, mo)
+        assert np.array_equal(mg, mo), (i, int((mg != mo).sum()))
+        assert compare_state(canon.parse(states[i]), so) == 0, i
+
+
+def _sample_pixels(H, W, seed, n=3000):
+    rng = np.random.default_rng(seed)
+    idx = set(rng.choice(H * W, size=n, replace=False).tolist())
+    for (y0, x0) in ((H // 3, W // 4), (2 * H // 3, W // 2)):
+        for y in range(y0, y0 + 4):
+            idx.update(range(y * W + x0, y * W + x0 + 128))
+    return np.array(sorted(idx))
+
+
+def test_serving_4k_stream_sampled_against_oracle(C):
+    """A 3840x2160 stream served one frame per submission beside a 640x480
+    stream admitted while it runs: the 4K stream's masks and state on sampled
+    pixels, and the small stream in full, against the oracle."""
+    import torch
+    spec4 = synth.preset("surveil-1920x1080-k5-occ05").with_(width=3840, height=2160, frames=36,
+                                                             n_train=20)
+    fr4 = synth.make_stream(spec4, threads=16)
+    p4 = gpu_params(C, 3840, 2160, c=3, K=5)
+    fr1 = _synth(640, 480, 40, 31)
+    p1 = gpu_params(C, 640, 480, c=3, K=5)
+    devs = [torch.from_numpy(fr4).cuda(), torch.from_numpy(fr1).cuda()]
+    masks = [torch.zeros((d.shape[0] - 20, d.shape[1] * d.shape[2]), dtype=torch.uint8, device="cuda")
+             for d in devs]
+    torch.cuda.synchronize()
+    srv = C.CogServer(hbm_budget=8 << 30, max_streams=4, depth=2)
+    ids = {0: srv.open(p4, devs[0][:20])}
+    nxt = {0: 0}
+    tag = 0
+    for step in range(24):
+        if step == 2:
+            ids[1] = srv.open(p1, devs[1][:20])
+            nxt[1] = 0
+        for i in ids:
+            f = nxt[i]
+            if f < devs[i].shape[0] - 20:
+                srv.submit(ids[i], devs[i][20 + f:21 + f], masks[i][f:f + 1], tag=tag, nframes=1)
+                nxt[i] = f + 1
+                tag += 1
+    srv.drain()
+    comps = srv.poll(max_n=tag + 8)
+    assert len(comps) == tag and all(c["status"] == 0 for c in comps)
+    states = {i: srv.export_state(ids[i]) for i in ids}
+    for i in ids:
+        srv.close_stream(ids[i])
+    srv.close()
+    m4 = masks[0].cpu().numpy()
+    P = 3840 * 2160
+    pix = _sample_pixels(2160, 3840, spec4.seed)
+    sub = fr4.reshape(len(fr4), P, 3)[:, pix][:, None]
+    po = orc_params_like(p4)
+    po.width, po.height = len(pix), 1
+    say("4K served stream against the oracle on", len(pix), "pixels")
+    mo, _, so = run_orc(po, sub, 20)
+    assert np.array_equal(m4[:, pix], mo), int((m4[:, pix] != mo).sum())
+    assert compare_state(canon.parse(states[0]), so, pix=pix) == 0
+    assert set(np.unique(m4)) <= {0, 255}
+    del m4, states[0]
+    m1 = masks[1].cpu().numpy()
+    mo, _, so = run_orc(orc_params_like(p1), fr1, 20)
+    assert np.array_equal(m1, mo), int((m1 != mo).sum())
+    assert compare_state(canon.parse(states[1]), so) == 0
