@@ -39,10 +39,12 @@ HEADLINE = "surveil-1920x1080-k5-occ05"
 SWEEP = ("surveil-1920x1080-k5-occ01", "surveil-1920x1080-k5-occ05",
          "surveil-1920x1080-k5-occ10", "surveil-1920x1080-k5-occ30")
 HBM_PEAK_GBS = 8000.0
-# vector ALU issue limit without packed or fused forms: 256 CU x 4 SIMD x 16
-# lanes x 2.4 GHz lane operations per second (one wave64 instruction per 4
-# cycles per SIMD)
-ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# vector ALU operation rate: 256 CU x 4 SIMD x 32 lanes per cycle x 2.4 GHz
+# lane operations per second, the rate behind the 157.3 TFLOP/s fp32 vector
+# figure (an FMA counts two flops).  (One wave64 instruction per 4 cycles per
+# SIMD would be half of it; the cascade's and the mixture's launches issue
+# VALU instructions faster than that, by their SQ counters.)
+ALU_PEAK_GOPS = 256 * 4 * 32 * 2.4
 LEGS = ("stream", "infos", "per_frame", "model", "sweep", "sampling", "grouping", "batch", "serve")
 GEN_THREADS = 16
 
@@ -119,6 +121,12 @@ def kernel_source_hash() -> str:
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def traffic_name(kernel, grid, workload):
+    """File name of a committed traffic summary of one kernel and grid."""
+    k = kernel.replace("<", "_").replace(">", "").replace(", ", "_")
+    return f"traffic_{k}_g{grid}_{workload}.txt"
 
 
 def profile_kv(name):
@@ -511,7 +519,7 @@ def main():
            "frac_of_copy": r(b_stream / launch_s / 1e9 / copy_gbs, 4),
            "dirty_record_px": dirty}
     grid = P if (args.tile or 64) == 64 else None  # work-items of the 64-pixel launch
-    tr = profile_kv(f"traffic_k_cascade_d_g{grid}_{spec.name}.txt")
+    tr = profile_kv(traffic_name(kname, grid, spec.name))
     if tr:
         hbm["traffic"] = int(float(tr["hbm_bytes_per_launch"]))
         hbm["traffic_gbs"] = r(hbm["traffic"] / launch_s / 1e9, 1)
@@ -552,7 +560,7 @@ def main():
                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r(ach / HBM_PEAK_GBS, 4),
                "frac_of_copy": r(ach / copy_gbs, 4), "bytes_per_px_frame": r(bpx, 3),
                "us_per_frame": us}
-        tpf = profile_kv(f"traffic_k_frame_g{(P + 255) // 256 * 64}_{spec.name}.txt")
+        tpf = profile_kv(traffic_name("k_frame<3, 5, false>", (P + 255) // 256 * 64, spec.name))
         if tpf:
             pfr["traffic_per_frame"] = int(float(tpf["hbm_bytes_per_launch"]))
             pfr["traffic_gbs"] = r(pfr["traffic_per_frame"] / (us * 1e-6) / 1e9, 1)
