@@ -536,7 +536,7 @@ def main():
                 "hbm": hbm,
                 "note": "achieved = wave64 VALU instructions of the launch (committed SQ counters, "
                         "same kernel, grid and workload) x 64 lanes / live launch time; peak = "
-                        "256 CU x 4 SIMD x 16 lanes x 2.4 GHz; the launch's HBM bytes are under hbm"}
+                        "256 CU x 4 SIMD x 32 lanes x 2.4 GHz; the launch's HBM bytes are under hbm"}
     elif dominant == "cascade":
         roof = {"bound": "hbm", "kernel": kname, "achieved": hbm["achieved_gbs"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm["frac"],
@@ -545,8 +545,8 @@ def main():
     else:
         bt = train_bytes(P, N, K)
         ach = bt / (s_cog["train_ms"] * 1e-3) / 1e9
-        trt = profile_kv(f"traffic_k_train_{spec.name}.txt")
-        roof = {"bound": "hbm", "kernel": "k_train<3, 5, false, true>", "achieved": r(ach, 1),
+        trt = profile_kv(traffic_name("k_train_prior<3, 5, false>", (P + 127) // 128 * 256, spec.name))
+        roof = {"bound": "hbm", "kernel": "k_train_prior<3, 5, false>", "achieved": r(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r(ach / HBM_PEAK_GBS, 4),
                 "traffic": int(float(trt["hbm_bytes_per_launch"])) if trt else None,
                 "alg_bytes_per_launch": int(bt), "launch_ms": r(s_cog["train_ms"])}

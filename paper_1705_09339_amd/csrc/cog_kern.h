@@ -531,13 +531,14 @@ __device__ __forceinline__ float confidence(const uint8_t *rec, const float (&x)
 }
 
 // ============================================================================
-// Training phase: one thread per pixel walks the N training frames.
+// Training phase: each pixel's N training frames are walked once for
 //  - integer KDE bin masses acc[c][b] += W[b][q(x)] (weights staged in LDS,
 //    level-major so one level's 16 weights are two 16-byte reads),
 //  - the residue histogram over max_c |x_j - x_{j-1}|,
 //  - the mixture warm-up (initialised from frame 0, stepped on 1..N-1).
 // Then the max-normalised u8 table, counts, mixture, running average (from
-// the dominant mode), previous frame and label are written once.
+// the dominant mode), previous frame and label are written once.  The
+// baseline mixture trains only the warm-up.
 // floor((255 a + floor(d / 2)) / d) for 0 <= a <= d, d > 0, exactly.  The
 // quotient is at most 255: a binary32 estimate is within one of it (its
 // relative error is below 2^-22), and two exact 64-bit comparisons correct it,
@@ -561,30 +562,16 @@ __device__ __forceinline__ uint32_t var_key(float S, float Q, float n) {
   return __float_as_uint(var) >> 16;
 }
 
-template <int C, int K, bool F32, bool PRIOR>
+// Warm-up of the plain mixture baseline: one thread per pixel steps its
+// mixture over the N training frames and stores it in the grouped layout.
+template <int C, int K, bool F32>
 __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, int64_t stride,
                                                int n, KParams kp) {
-  // the cascade keeps per-pixel mixture records; the baseline 64-pixel groups
-  constexpr bool with_prior = PRIOR, aos = PRIOR;
-  __shared__ uint4 s_w[256 * kBins * 2 / 16];
-  for (int i = threadIdx.x; i < 256 * kBins * 2 / 16; i += kNT)
-    s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
-  __syncthreads();
-
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
   const bool valid = p < b.P;
   bool lab = false;
   if (valid) {
-    uint32_t acc[C][kBins];
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-#pragma unroll
-      for (int q = 0; q < kBins; ++q) acc[c][q] = 0u;
-    uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
-    // grouping features: sums over the warm-up of the dominant component's
-    // adapted variance and weight and of their squares
-    float sv = 0.0f, qv = 0.0f, sw = 0.0f, qw = 0.0f;
     float x[C], xp[C], xn[C];
     Mix<C, K> m;
     load_px<C, F32>(frames, p, x);
@@ -597,81 +584,149 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
 #pragma unroll
         for (int c = 0; c < C; ++c) x[c] = xn[c];
         if (j + 1 < n) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
-      }
-      if constexpr (with_prior) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const int v = quant<F32>(x[c], kp);
-          const uint4 lo = s_w[2 * v], hi = s_w[2 * v + 1];
-          const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            acc[c][2 * q] += wd[q] & 0xffffu;
-            acc[c][2 * q + 1] += wd[q] >> 16;
-          }
-        }
-      }
-      if (j >= 1) {
-        if constexpr (with_prior) {
-          const float dl = frame_delta<C>(x, xp);
-          // residue bins [0, e1), [e1, e2), [e2, inf) counted without branches
-          const bool r0 = dl < kp.res_e1, r1 = !r0 && dl < kp.res_e2;
-          cnt0 += r0 ? 1u : 0u;
-          cnt1 += r1 ? 1u : 0u;
-          cnt2 += (!r0 && !r1) ? 1u : 0u;
-        }
         int l, mp;
         mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
         lab = l != 0;
-        if constexpr (with_prior) {
-          sv = sv + m.var[0];
-          qv = qv + m.var[0] * m.var[0];
-          sw = sw + m.w[0];
-          qw = qw + m.w[0] * m.w[0];
-        }
       }
 #pragma unroll
       for (int c = 0; c < C; ++c) xp[c] = x[c];
     }
+    grp_store<C, K>(b.gmm, p, m);
+    store_px<C, F32>(b.prev, p, xp);
+  }
+  const unsigned long long bal = __ballot(lab);
+  const int64_t w0 = p - lane;
+  if (lane == 0 && w0 < b.P) b.labels[w0 >> 6] = bal;
+}
 
-    if constexpr (with_prior) {
-      constexpr int PB = prior_bytes(C);
-      uint32_t words[PB / 4];
+// Training of the cascade (§2 "Scene Prior", "Cascade of Gaussians CoG") in
+// two wave roles: a workgroup covers kTrainPx pixels with twice as many
+// threads.  Its first waves accumulate the kernel-density bins and the
+// residue counts and write the prior record; its other waves run the mixture
+// warm-up over the same pixels and write the mixture, running average,
+// previous value, label and grouping keys.  The two roles read the same
+// frames and run concurrently.  Each holds only its own accumulators (the
+// 48 bin accumulators, or the mixture), so a thread needs about half the
+// registers of one that holds both and more than twice as many waves stay
+// resident.
+constexpr int kTrainPx = 128;
+
+template <int C, int K, bool F32>
+__global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const void *frames,
+                                                        int64_t stride, int n, KParams kp) {
+  __shared__ uint4 s_w[256 * kBins * 2 / 16];
+  for (int i = threadIdx.x; i < 256 * kBins * 2 / 16; i += 2 * kTrainPx)
+    s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
+  __syncthreads();
+
+  const bool prior_role = threadIdx.x < kTrainPx;  // wave-uniform
+  const int t = prior_role ? threadIdx.x : threadIdx.x - kTrainPx;
+  const int lane = t & 63;
+  const int64_t p = (int64_t)blockIdx.x * kTrainPx + t;
+  const bool valid = p < b.P;
+  if (prior_role) {
+    if (!valid) return;
+    uint32_t acc[C][kBins];
 #pragma unroll
-      for (int i = 0; i < PB / 4; ++i) words[i] = 0u;
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q = 0; q < kBins; ++q) acc[c][q] = 0u;
+    uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
+    float x[C], xp[C], xn[C];
+    load_px<C, F32>(frames, p, x);
+    if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
+    for (int j = 0; j < n; ++j) {
+      if (j >= 1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = xn[c];
+        if (j + 1 < n) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
+      }
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        uint32_t amax = 0;
+        const int v = quant<F32>(x[c], kp);
+        const uint4 lo = s_w[2 * v], hi = s_w[2 * v + 1];
+        const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-        for (int q = 0; q < kBins; ++q) amax = acc[c][q] > amax ? acc[c][q] : amax;
-#pragma unroll
-        for (int q = 0; q < kBins; ++q) {
-          const uint32_t t = amax ? round_ratio255(acc[c][q], amax) : 0u;
-          const int byte = c * kBins + q;
-          words[byte >> 2] |= (t & 0xffu) << (8 * (byte & 3));
+        for (int q = 0; q < 8; ++q) {
+          acc[c][2 * q] += wd[q] & 0xffffu;
+          acc[c][2 * q + 1] += wd[q] >> 16;
         }
       }
-      // confidence weights a, b, g = counts / (N - 1), divided once here
-      words[(C * kBins) / 4] = __float_as_uint((float)cnt0 / kp.nm1);
-      words[(C * kBins) / 4 + 1] = __float_as_uint((float)cnt1 / kp.nm1);
-      words[(C * kBins) / 4 + 2] = __float_as_uint((float)cnt2 / kp.nm1);
-      *reinterpret_cast<uint2 *>(b.cnt + p * 4) =
-          make_uint2((cnt0 & 0xffffu) | (cnt1 << 16), cnt2 & 0xffffu);
-      uint4 *dst = reinterpret_cast<uint4 *>(b.prior + p * PB);
+      if (j >= 1) {
+        const float dl = frame_delta<C>(x, xp);
+        // residue bins [0, e1), [e1, e2), [e2, inf) counted without branches
+        const bool r0 = dl < kp.res_e1, r1 = !r0 && dl < kp.res_e2;
+        cnt0 += r0 ? 1u : 0u;
+        cnt1 += r1 ? 1u : 0u;
+        cnt2 += (!r0 && !r1) ? 1u : 0u;
+      }
 #pragma unroll
-      for (int i = 0; i < PB / 16; ++i)
-        dst[i] = make_uint4(words[4 * i], words[4 * i + 1], words[4 * i + 2], words[4 * i + 3]);
-
-      constexpr int RG = rga_floats(C);
-      float *rg = b.rga + p * RG;
-#pragma unroll
-      for (int c = 0; c < C; ++c) rg[c] = m.mu[0][c];
-      rg[C] = m.var[0];
-      b.sat[p] = 0;  // no confident frame yet (sampling)
-      b.gkey[p] = make_uint2(var_key(sv, qv, kp.nm1), var_key(sw, qw, kp.nm1));
+      for (int c = 0; c < C; ++c) xp[c] = x[c];
     }
-    if constexpr (aos) rec_store<C, K>(b.gmm + p * rec_floats(C, K), m);
-    else grp_store<C, K>(b.gmm, p, m);
+    constexpr int PB = prior_bytes(C);
+    uint32_t words[PB / 4];
+#pragma unroll
+    for (int i = 0; i < PB / 4; ++i) words[i] = 0u;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      uint32_t amax = 0;
+#pragma unroll
+      for (int q = 0; q < kBins; ++q) amax = acc[c][q] > amax ? acc[c][q] : amax;
+#pragma unroll
+      for (int q = 0; q < kBins; ++q) {
+        const uint32_t tq = amax ? round_ratio255(acc[c][q], amax) : 0u;
+        const int byte = c * kBins + q;
+        words[byte >> 2] |= (tq & 0xffu) << (8 * (byte & 3));
+      }
+    }
+    // confidence weights a, b, g = counts / (N - 1), divided once here
+    words[(C * kBins) / 4] = __float_as_uint((float)cnt0 / kp.nm1);
+    words[(C * kBins) / 4 + 1] = __float_as_uint((float)cnt1 / kp.nm1);
+    words[(C * kBins) / 4 + 2] = __float_as_uint((float)cnt2 / kp.nm1);
+    *reinterpret_cast<uint2 *>(b.cnt + p * 4) =
+        make_uint2((cnt0 & 0xffffu) | (cnt1 << 16), cnt2 & 0xffffu);
+    uint4 *dst = reinterpret_cast<uint4 *>(b.prior + p * PB);
+#pragma unroll
+    for (int i = 0; i < PB / 16; ++i)
+      dst[i] = make_uint4(words[4 * i], words[4 * i + 1], words[4 * i + 2], words[4 * i + 3]);
+    return;
+  }
+
+  // the mixture warm-up (initialised from frame 0, stepped on 1..N-1)
+  bool lab = false;
+  if (valid) {
+    // grouping features: sums over the warm-up of the dominant component's
+    // adapted variance and weight and of their squares
+    float sv = 0.0f, qv = 0.0f, sw = 0.0f, qw = 0.0f;
+    float x[C], xp[C], xn[C];
+    Mix<C, K> m;
+    load_px<C, F32>(frames, p, x);
+    mix_init<C, K>(m, x, kp.var_init);
+    if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
+    for (int j = 0; j < n; ++j) {
+      if (j >= 1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = xn[c];
+        if (j + 1 < n) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
+        int l, mp;
+        mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
+        lab = l != 0;
+        sv = sv + m.var[0];
+        qv = qv + m.var[0] * m.var[0];
+        sw = sw + m.w[0];
+        qw = qw + m.w[0] * m.w[0];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) xp[c] = x[c];
+    }
+    constexpr int RG = rga_floats(C);
+    float *rg = b.rga + p * RG;
+#pragma unroll
+    for (int c = 0; c < C; ++c) rg[c] = m.mu[0][c];
+    rg[C] = m.var[0];
+    b.sat[p] = 0;  // no confident frame yet (sampling)
+    b.gkey[p] = make_uint2(var_key(sv, qv, kp.nm1), var_key(sw, qw, kp.nm1));
+    rec_store<C, K>(b.gmm + p * rec_floats(C, K), m);
     store_px<C, F32>(b.prev, p, xp);
   }
   const unsigned long long bal = __ballot(lab);
@@ -2067,11 +2122,10 @@ hipError_t launch_train_k(int C, bool f32in, bool prior, const Buffers &b, const
   const unsigned g = grid_for(b.P, kNT);
 #define COG_TRAIN(CC, FF, _)                                                                   \
   if (prior)                                                                                   \
-    hipLaunchKernelGGL((k_train<CC, K, FF, true>), dim3(g), dim3(kNT), 0, s, b, frames, stride, \
-                       n, kp);                                                                 \
+    hipLaunchKernelGGL((k_train_prior<CC, K, FF>), dim3(grid_for(b.P, kTrainPx)),             \
+                       dim3(2 * kTrainPx), 0, s, b, frames, stride, n, kp);                    \
   else                                                                                         \
-    hipLaunchKernelGGL((k_train<CC, K, FF, false>), dim3(g), dim3(kNT), 0, s, b, frames, stride, \
-                       n, kp)
+    hipLaunchKernelGGL((k_train<CC, K, FF>), dim3(g), dim3(kNT), 0, s, b, frames, stride, n, kp)
   COG_C_CASES(COG_TRAIN, 0)
 #undef COG_TRAIN
   return hipGetLastError();
