@@ -31,6 +31,7 @@ struct orc_state {
   float *prev;      /* [npix][C] previous frame value */
   uint16_t *sat;    /* [npix] consecutive confident evaluated frames (sampling) */
   float *feat;      /* [npix][4] warm-up sums of the dominant slot: S_v, Q_v, S_w, Q_w */
+  uint8_t *grp;     /* [npix] group whose shared S1 variance the pixel takes, 255: none */
   uint16_t W[NBINS][NLEVELS];
 };
 
@@ -218,7 +219,10 @@ orc_state *orc_create(const orc_params *p) {
   s->prev = (float *)calloc((size_t)(P * C), sizeof(float));
   s->sat = (uint16_t *)calloc((size_t)P, sizeof(uint16_t));
   s->feat = (float *)calloc((size_t)P * 4, sizeof(float));
+  s->grp = (uint8_t *)malloc((size_t)P);
+  if (s->grp) memset(s->grp, 255, (size_t)P);
   if (!s->gmm || !s->rga || !s->table || !s->cnt || !s->label || !s->prev || !s->sat || !s->feat ||
+      !s->grp ||
       orc_kde_weights((double)p->kde_h, &s->W[0][0]) != 0) {
     orc_destroy(s);
     return NULL;
@@ -236,6 +240,7 @@ void orc_destroy(orc_state *s) {
   free(s->prev);
   free(s->sat);
   free(s->feat);
+  free(s->grp);
   free(s);
 }
 
@@ -375,6 +380,7 @@ int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
     float *xp = s->prev + px * C;
     float *rg = s->rga + px * (C + 1);
     float *comp = s->gmm + px * K * F;
+    const int shared = s->grp[px] != 255; /* the S1 variance is the group's, fixed */
     int lab;
 
     /* S0: consistent hypothesis propagation (frame differencing) */
@@ -400,7 +406,7 @@ int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
         float e = x[c] - rg[c];
         sr = sr + e * e;
       }
-      rg[C] = fmax0(p->var_min, oar * rg[C] + p->alpha_rga * sr);
+      if (!shared) rg[C] = fmax0(p->var_min, oar * rg[C] + p->alpha_rga * sr);
       n1++;
       goto done;
     }
@@ -434,7 +440,7 @@ int orc_step(orc_state *s, const void *frame, uint8_t *mask, int64_t *info) {
       if (lab == ORC_BG) {
         n3bg++;
         for (int c = 0; c < C; ++c) rg[c] = comp[mp * F + 1 + c];
-        rg[C] = comp[mp * F + 1 + C];
+        if (!shared) rg[C] = comp[mp * F + 1 + C];
       }
     }
   done:
@@ -623,10 +629,68 @@ int orc_group_run(const uint32_t *keys, int64_t P, uint8_t *map, double *info) {
   return 0;
 }
 
-/* ---- canonical export: 64-byte header (version 2), then sections each
+/* ---- one shared parameter set per group (§2 "Clustering Similar
+ * Background", the list's last item and eq. 3): the pixels of a group share
+ * the variance of the first, dominant cascade level (the running Gaussian
+ * average), fitted once as the mean of the members' variances, so that
+ * the region has one variance parameter and its pixels no longer update it.
+ * The mean is taken exactly on a fixed-point grid: each member's variance
+ * rounded to a multiple of 2^-16 (binary64 rint, ties to even), summed as
+ * integers, then divided once in binary64 and rounded to binary32, and held
+ * at var_min or above.  Means keep adapting per pixel.  map: group 0..2 per
+ * pixel (255: not grouped), e.g. the map of orc_group; NULL ungroups every
+ * pixel, which then adapts its variance again from the value it holds.
+ * gvar (may be NULL): the 3 shared variances (0 for an empty group). ------ */
+int orc_group_share(orc_state *s, const uint8_t *map, float *gvar) {
+  if (!s || s->n_train == 0) return -1;
+  const int C = s->p.channels;
+  const int64_t P = s->npix;
+  uint64_t cnt[ORC_NGROUPS] = {0}, sum[ORC_NGROUPS] = {0};
+  float v[ORC_NGROUPS] = {0.0f, 0.0f, 0.0f};
+  if (map) {
+    for (int64_t px = 0; px < P; ++px) {
+      const int g = map[px];
+      if (g == 255) continue;
+      if (g >= ORC_NGROUPS) return -1;
+      const double q = rint((double)s->rga[px * (C + 1) + C] * 65536.0);
+      if (!(q >= 0.0 && q < 9007199254740992.0)) return -1; /* 2^53 */
+      cnt[g]++;
+      sum[g] += (uint64_t)q;
+    }
+    for (int g = 0; g < ORC_NGROUPS; ++g) {
+      if (!cnt[g]) continue;
+      const float m = (float)((double)sum[g] / 65536.0 / (double)cnt[g]);
+      v[g] = fmax0(s->p.var_min, m);
+    }
+  }
+  orc_group_set(s, map, v);
+  if (gvar)
+    for (int g = 0; g < ORC_NGROUPS; ++g) gvar[g] = v[g];
+  return 0;
+}
+
+/* The members of each group take the given shared variance gvar[g] (no
+ * fitting); the others keep their own.  map NULL ungroups every pixel. */
+int orc_group_set(orc_state *s, const uint8_t *map, const float *gvar) {
+  if (!s || s->n_train == 0 || (map && !gvar)) return -1;
+  const int C = s->p.channels;
+  const int64_t P = s->npix;
+  if (map)
+    for (int64_t px = 0; px < P; ++px)
+      if (map[px] != 255 && map[px] >= ORC_NGROUPS) return -1;
+  for (int64_t px = 0; px < P; ++px) {
+    const int g = map ? map[px] : 255;
+    s->grp[px] = (uint8_t)g;
+    if (g != 255) s->rga[px * (C + 1) + C] = gvar[g];
+  }
+  return 0;
+}
+
+/* ---- canonical export: 64-byte header (version 3), then sections each
  * padded to 64 B: gmm f32[P][K][C+2], rga f32[P][C+1], table u8[P][C][16],
  * cnt u16[P][3], label u8[P], prev f32[P][C], sat u16[P], gkey u32[P][2]
- * (the grouping keys of the training warm-up). ----------------------------- */
+ * (the grouping keys of the training warm-up), shared u8[P] (1 where the
+ * pixel takes its group's shared variance). -------------------------------- */
 static size_t pad64(size_t n) { return (n + 63) & ~(size_t)63; }
 
 size_t orc_canonical_bytes(const orc_params *p) {
@@ -634,7 +698,7 @@ size_t orc_canonical_bytes(const orc_params *p) {
   const size_t P = (size_t)p->width * p->height;
   const size_t C = (size_t)p->channels, K = (size_t)p->K;
   return 64 + pad64(P * K * (C + 2) * 4) + pad64(P * (C + 1) * 4) + pad64(P * C * NBINS) +
-         pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2) + pad64(P * 8);
+         pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2) + pad64(P * 8) + pad64(P);
 }
 
 int orc_export(const orc_state *s, void *dst, size_t bytes) {
@@ -645,7 +709,7 @@ int orc_export(const orc_state *s, void *dst, size_t bytes) {
   const size_t C = (size_t)p->channels, K = (size_t)p->K;
   char *o = (char *)dst;
   memset(o, 0, orc_canonical_bytes(p));
-  uint32_t hdr32[2] = {0x31474F43u, 2u};
+  uint32_t hdr32[2] = {0x31474F43u, 3u};
   int32_t hdri[6] = {p->width, p->height, p->channels, p->K, p->dtype, s->n_train};
   int64_t fr = s->frame;
   memcpy(o, hdr32, 8);
@@ -667,5 +731,7 @@ int orc_export(const orc_state *s, void *dst, size_t bytes) {
   memcpy(o + off, s->sat, P * 2);
   off += pad64(P * 2);
   if (s->n_train >= 2) orc_group_keys(s, (uint32_t *)(o + off));
+  off += pad64(P * 8);
+  for (size_t px = 0; px < P; ++px) o[off + px] = s->grp[px] != 255 ? 1 : 0;
   return 0;
 }

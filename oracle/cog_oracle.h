@@ -87,6 +87,16 @@ int orc_group(const orc_state *s, uint8_t *map, double *info);
 /* The clustering and eq. 3 band alone, on given keys (P x 2 u32, P >= 1). */
 int orc_group_run(const uint32_t *keys, int64_t P, uint8_t *map, double *info);
 
+/* One shared parameter set per group (eq. 3 and the list before it): the
+ * pixels of each group take one shared variance of the running Gaussian
+ * average (S1), the exact mean of the members' variances on a 2^-16 grid,
+ * at least var_min, and stop adapting it; means still adapt per pixel.
+ * map: P bytes, group 0..2 or 255 (not grouped); NULL ungroups all.
+ * gvar (may be NULL): the 3 shared variances, 0 for an empty group. */
+int orc_group_share(orc_state *s, const uint8_t *map, float *gvar);
+/* The sharing alone with given values: members of group g take gvar[g]. */
+int orc_group_set(orc_state *s, const uint8_t *map, const float *gvar);
+
 size_t orc_canonical_bytes(const orc_params *p);
 int orc_export(const orc_state *s, void *dst, size_t bytes);
 

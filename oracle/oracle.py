@@ -83,6 +83,8 @@ def lib():
         L.orc_group_keys.argtypes = [ct.c_void_p, P(ct.c_uint32)]
         L.orc_group.argtypes = [ct.c_void_p, P(ct.c_uint8), P(ct.c_double)]
         L.orc_group_run.argtypes = [P(ct.c_uint32), ct.c_int64, P(ct.c_uint8), P(ct.c_double)]
+        L.orc_group_share.argtypes = [ct.c_void_p, P(ct.c_uint8), P(ct.c_float)]
+        L.orc_group_set.argtypes = [ct.c_void_p, P(ct.c_uint8), P(ct.c_float)]
         L.orc_canonical_bytes.argtypes = [P(OrcParams)]
         L.orc_canonical_bytes.restype = ct.c_size_t
         L.orc_export.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t]
@@ -223,6 +225,31 @@ class Oracle:
                            info.ctypes.data_as(ct.POINTER(ct.c_double))) != 0:
             raise RuntimeError("orc_group failed (train first)")
         return m, _group_info(info)
+
+    def group_share(self, group_map) -> np.ndarray:
+        """Shared S1 variance per group for the pixels of group_map ([P] u8, 0..2 or 255;
+        None ungroups every pixel); returns the 3 shared variances."""
+        gv = np.zeros(3, dtype=np.float32)
+        if group_map is None:
+            mp = ct.POINTER(ct.c_uint8)()
+        else:
+            m = np.ascontiguousarray(group_map, dtype=np.uint8).reshape(-1)
+            if m.size != self.npix:
+                raise ValueError("group map must hold one byte per pixel")
+            mp = m.ctypes.data_as(ct.POINTER(ct.c_uint8))
+        if lib().orc_group_share(self._h, mp, gv.ctypes.data_as(ct.POINTER(ct.c_float))) != 0:
+            raise RuntimeError("orc_group_share failed (train first; groups 0..2 or 255)")
+        return gv
+
+    def group_set(self, group_map, gvar) -> None:
+        """The members of group g take the shared variance gvar[g] (no fitting)."""
+        m = np.ascontiguousarray(group_map, dtype=np.uint8).reshape(-1)
+        g = np.ascontiguousarray(gvar, dtype=np.float32).reshape(3)
+        if m.size != self.npix:
+            raise ValueError("group map must hold one byte per pixel")
+        if lib().orc_group_set(self._h, m.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                               g.ctypes.data_as(ct.POINTER(ct.c_float))) != 0:
+            raise RuntimeError("orc_group_set failed")
 
     def export(self) -> bytes:
         nb = lib().orc_canonical_bytes(ct.byref(self.params))

@@ -54,7 +54,7 @@ def test_constant_input_skip_counts_closed_form(w, h, W_frames, period):
         assert info["n0"] == P - exp and info["n1"] == info["n2"] == info["n3"] == 0
         assert (m == 0).all()
     st = canon.parse(o.export())
-    assert st["version"] == 2
+    assert st["version"] == 3
     # each pixel counted its evaluated frames (all confident)
     evaluated = np.zeros(P, dtype=np.int64)
     for t in range(N, N + steps):
