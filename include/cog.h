@@ -177,10 +177,12 @@ void cog_destroy(cog_ctx *h);
  * then sections each padded to 64 bytes: gmm f32[P][K][C+2] (w, mu[C], var in
  * rank order), rga f32[P][C+1] (mu_r[C], var_r), table u8[P][C][16],
  * cnt u16[P][3], label u8[P] (0/1), prev f32[P][C], sat u16[P] (sampling
- * counters) and gkey u32[P][2] (grouping keys): version 2 of the layout;
- * version-1 states, without the last two sections, are still imported with
- * zero counters and keys.  For checkpoint/resume and tests;
- * synchronous; host buffers only. */
+ * counters), gkey u32[P][2] (grouping keys) and shared u8[P] (1 where the
+ * pixel takes its group's shared variance, cog_group_share): version 3 of the
+ * layout.  Version-2 states (without the last section) are imported with no
+ * pixel shared, version-1 states (without the last three) also with zero
+ * counters and keys.  For checkpoint/resume and tests; synchronous; host
+ * buffers only. */
 cog_status cog_canonical_bytes(const cog_params *p, size_t *bytes);
 cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes);
 cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes);
@@ -212,6 +214,27 @@ typedef struct {
 } cog_group_info;
 cog_status cog_group_background(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,
                                 cog_group_info *info);
+
+/* One shared parameter set per group (§2 "Clustering Similar Background",
+ * the last item of its list and eq. 3): the pixels of each group take one
+ * variance for their running Gaussian average (the first, dominant cascade
+ * level), fitted once as the mean of the members' current variances, and no
+ * longer adapt it; their means keep adapting per pixel.  The mean is exact
+ * on a fixed-point grid: each member's variance rounded to a multiple of
+ * 2^-16 (binary64 rint, ties to even), the integers summed, one binary64
+ * division, then binary32, held at var_min or above.
+ * map (P bytes, device when map_on_device != 0, else host): group 0..2 per
+ * pixel, 255 for a pixel outside every group, e.g. the map written by
+ * cog_group_background; NULL ungroups every pixel (each then adapts its
+ * variance again from the value it holds).  Pixels outside the groups keep
+ * their own variance.  gvar_out (3 floats, may be NULL): the shared
+ * variances, 0 for an empty group.  Training clears the sharing.  The flag
+ * travels in the canonical state's shared section.  Synchronous; uses
+ * temporary device memory.  COG_E_STATE before training, COG_E_UNSUPPORTED
+ * on the baseline path, COG_E_INVALID for a map value other than 0..2 and
+ * 255 or a member variance of 2^37 or more (nothing is changed then). */
+cog_status cog_group_share(cog_ctx *h, const uint8_t *map, int32_t map_on_device,
+                           float *gvar_out);
 
 /* The same grouping without any device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses that

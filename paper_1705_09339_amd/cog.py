@@ -133,6 +133,7 @@ def _load(path: str = LIB_PATH):
         "cog_last_error": ([V], ct.c_char_p),
         "cog_group_background": ([V, V, ct.c_int32, P(cog_group_info)], ct.c_int),
         "cog_group_background_noalloc": ([V, V, ct.c_int32, P(cog_group_info)], ct.c_int),
+        "cog_group_share": ([V, V, ct.c_int32, P(ct.c_float)], ct.c_int),
         "cog_batch_create": ([V, ct.c_int32, P(V)], ct.c_int),
         "cog_batch_tick": ([V, P(cog_tick_item), ct.c_int32], ct.c_int),
         "cog_batch_autotune": ([V, P(cog_tick_item), ct.c_int32, ct.c_int32, P(cog_schedule)], ct.c_int),
@@ -161,7 +162,7 @@ lib = _load()
 EXPORTED = ("cog_default_params", "cog_state_bytes", "cog_canonical_bytes", "cog_create",
             "cog_train_prior", "cog_step", "cog_step_frames", "cog_reset", "cog_destroy",
             "cog_export_state", "cog_import_state", "cog_kde_weights", "cog_last_error",
-            "cog_group_background", "cog_group_background_noalloc",
+            "cog_group_background", "cog_group_background_noalloc", "cog_group_share",
             "cog_batch_create", "cog_batch_tick", "cog_batch_autotune", "cog_batch_set_schedule",
             "cog_batch_get_schedule", "cog_batch_destroy",
             "cog_server_create", "cog_server_open", "cog_server_submit", "cog_server_close",
@@ -309,6 +310,17 @@ def cog_group_background_noalloc(h: int, map_out=None) -> dict:
 COG_NOALLOC_MAX_PIXELS = 1 << 23
 
 
+def cog_group_share(h: int, group_map=None) -> np.ndarray:
+    """One shared running-average variance per group for the pixels of
+    group_map (P bytes, numpy or torch; 0..2, 255 = outside every group);
+    None ungroups every pixel.  Returns the 3 shared variances."""
+    gv = np.zeros(3, dtype=np.float32)
+    mp, mdev, keep = _ptr(group_map)
+    _check(lib.cog_group_share(h, mp, mdev, gv.ctypes.data_as(ct.POINTER(ct.c_float))), h)
+    del keep
+    return gv
+
+
 def cog_last_error(h: Optional[int] = None) -> str:
     m = lib.cog_last_error(h)
     return m.decode() if m else ""
@@ -335,6 +347,9 @@ class CogStream:
 
     def group(self, map_out=None) -> dict:
         return cog_group_background(self.h, map_out)
+
+    def share(self, group_map=None):
+        return cog_group_share(self.h, group_map)
 
     def export_state(self) -> bytes:
         return cog_export_state(self.h, self.params)

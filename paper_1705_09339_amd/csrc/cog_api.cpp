@@ -485,7 +485,7 @@ cog_status cog_canonical_bytes(const cog_params *p, size_t *bytes) {
   if (!bytes) return fail(nullptr, COG_E_INVALID, "bytes is NULL");
   const size_t P = (size_t)p->width * p->height, C = (size_t)p->channels, K = (size_t)p->K;
   *bytes = 64 + pad64(P * K * (C + 2) * 4) + pad64(P * (C + 1) * 4) + pad64(P * C * 16) +
-           pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2) + pad64(P * 8);
+           pad64(P * 3 * 2) + pad64(P) + pad64(P * C * 4) + pad64(P * 2) + pad64(P * 8) + pad64(P);
   return COG_OK;
 }
 
@@ -673,7 +673,7 @@ cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes) {
   const size_t P = (size_t)pl.P, C = (size_t)pl.C, K = (size_t)pl.K;
   char *o = static_cast<char *>(host_dst);
   std::memset(o, 0, need);
-  const uint32_t h32[2] = {kMagic, 2u};
+  const uint32_t h32[2] = {kMagic, 3u};
   const int32_t hi[6] = {h->p.width, h->p.height, h->p.channels, h->p.K, h->p.dtype, h->n_train};
   std::memcpy(o, h32, 8);
   std::memcpy(o + 8, hi, 24);
@@ -694,10 +694,12 @@ cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes) {
   }
   off += pad64(P * K * (C + 2) * 4);
   if (aos) {
-    const float *rr = reinterpret_cast<const float *>(raw.data() + pl.off_rga);
-    float *r = reinterpret_cast<float *>(o + off);
+    // the stored variance carries the pixel's shared flag in its sign bit
+    const uint32_t *rr = reinterpret_cast<const uint32_t *>(raw.data() + pl.off_rga);
+    uint32_t *r = reinterpret_cast<uint32_t *>(o + off);
     for (size_t p = 0; p < P; ++p)
-      for (size_t c = 0; c <= C; ++c) r[p * (C + 1) + c] = rr[p * pl.RG + c];
+      for (size_t c = 0; c <= C; ++c)
+        r[p * (C + 1) + c] = rr[p * pl.RG + c] & (c == C ? 0x7fffffffu : 0xffffffffu);
   }
   off += pad64(P * (C + 1) * 4);
   if (aos) {
@@ -725,6 +727,12 @@ cog_status cog_export_state(cog_ctx *h, void *host_dst, size_t bytes) {
   if (aos) std::memcpy(o + off, raw.data() + pl.off_sat, P * 2);
   off += pad64(P * 2);
   if (aos) std::memcpy(o + off, raw.data() + pl.off_gkey, P * 8);
+  off += pad64(P * 8);
+  if (aos) {
+    const uint32_t *rr = reinterpret_cast<const uint32_t *>(raw.data() + pl.off_rga);
+    uint8_t *sh = reinterpret_cast<uint8_t *>(o + off);
+    for (size_t p = 0; p < P; ++p) sh[p] = (uint8_t)(rr[p * pl.RG + C] >> 31);
+  }
   return COG_OK;
 }
 
@@ -737,7 +745,9 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
   std::memcpy(&ver, in + 4, 4);
   size_t need = 0;
   cog_canonical_bytes(&h->p, &need);
-  // version 1 has no saturation and grouping-key sections
+  // version 1 has no saturation, grouping-key and shared sections, version 2
+  // no shared section
+  if (ver <= 2u) need -= pad64((size_t)h->plan.P);
   if (ver == 1u) need -= pad64((size_t)h->plan.P * 2) + pad64((size_t)h->plan.P * 8);
   if (bytes < need) return fail(h, COG_E_INVALID, "buffer smaller than the canonical state");
   uint32_t h32[2];
@@ -746,7 +756,7 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
   std::memcpy(h32, in, 8);
   std::memcpy(hi, in + 8, 24);
   std::memcpy(&frame, in + 32, 8);
-  if (h32[0] != kMagic || (h32[1] != 1u && h32[1] != 2u))
+  if (h32[0] != kMagic || h32[1] < 1u || h32[1] > 3u)
     return fail(h, COG_E_INVALID, "not a canonical state");
   if (hi[0] != h->p.width || hi[1] != h->p.height || hi[2] != h->p.channels || hi[3] != h->p.K ||
       hi[4] != h->p.dtype)
@@ -768,10 +778,11 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
       }
   off += pad64(P * K * (C + 2) * 4);
   if (aos) {
-    const float *r = reinterpret_cast<const float *>(in + off);
-    float *rr = reinterpret_cast<float *>(raw.data() + pl.off_rga);
+    const uint32_t *r = reinterpret_cast<const uint32_t *>(in + off);
+    uint32_t *rr = reinterpret_cast<uint32_t *>(raw.data() + pl.off_rga);
     for (size_t p = 0; p < P; ++p)
-      for (size_t c = 0; c <= C; ++c) rr[p * pl.RG + c] = r[p * (C + 1) + c];
+      for (size_t c = 0; c <= C; ++c)
+        rr[p * pl.RG + c] = r[p * (C + 1) + c] & (c == C ? 0x7fffffffu : 0xffffffffu);
   }
   off += pad64(P * (C + 1) * 4);
   if (aos) {
@@ -813,6 +824,13 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
   if (aos && ver >= 2u) std::memcpy(raw.data() + pl.off_sat, in + off, P * 2);
   off += pad64(P * 2);
   if (aos && ver >= 2u) std::memcpy(raw.data() + pl.off_gkey, in + off, P * 8);
+  off += pad64(P * 8);
+  if (aos && ver >= 3u) {
+    const uint8_t *sh = reinterpret_cast<const uint8_t *>(in + off);
+    uint32_t *rr = reinterpret_cast<uint32_t *>(raw.data() + pl.off_rga);
+    for (size_t p = 0; p < P; ++p)
+      if (sh[p]) rr[p * pl.RG + C] |= 0x80000000u;
+  }
   hipError_t e = hipMemcpyAsync(h->dstate, raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "state upload");
@@ -820,6 +838,64 @@ cog_status cog_import_state(cog_ctx *h, const void *host_src, size_t bytes) {
   h->frame = frame;
   h->kp = make_kparams(&h->p, h->n_train);
   return COG_OK;
+}
+
+cog_status cog_group_share(cog_ctx *h, const uint8_t *map, int32_t map_on_device,
+                           float *gvar_out) {
+  cog_status s = group_check(h);
+  if (s != COG_OK) return s;
+  const Plan &pl = h->plan;
+  const int64_t P = pl.P;
+  const int nb = cog::group_blocks(P);
+  constexpr int W = 2 * cog::kGroups + 1;
+  hipStream_t st = h->stream;
+  uint8_t *dmap = nullptr;
+  uint64_t *part = nullptr;
+  const bool copy_map = map && !map_on_device;
+  if ((copy_map && hipMalloc((void **)&dmap, (size_t)P) != hipSuccess) ||
+      hipMalloc((void **)&part, ((size_t)nb * W + W) * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    if (dmap) (void)hipFree(dmap);
+    return fail(h, COG_E_OOM, "sharing scratch allocation failed");
+  }
+  cog_status rc = COG_OK;
+  auto check = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess && rc == COG_OK) rc = hip_fail(h, e, what);
+    return rc == COG_OK;
+  };
+  const uint8_t *m = copy_map ? dmap : map;
+  cog::ShareVars v{};
+  if (map) {
+    uint64_t row[W] = {0};
+    if (copy_map) check(hipMemcpyAsync(dmap, map, (size_t)P, hipMemcpyHostToDevice, st), "copy");
+    if (rc == COG_OK &&
+        check(cog::launch_share_sum(h->buf.rga, pl.RG, pl.C, P, m, part, st), "sharing launch") &&
+        check(cog::launch_part_reduce(part, nb, W, 0u, 0u, part + (size_t)nb * W, st),
+              "sharing launch") &&
+        check(hipMemcpyAsync(row, part + (size_t)nb * W, sizeof(row), hipMemcpyDeviceToHost, st),
+              "copy"))
+      check(hipStreamSynchronize(st), "sharing");
+    if (rc == COG_OK && row[W - 1] != 0)
+      rc = fail(h, COG_E_INVALID, "group map holds a value other than 0..2 and 255, or a variance "
+                                  "beyond 2^37");
+    // the exact member mean on the 2^-16 grid, one binary64 division, then
+    // binary32, held at var_min or above
+    for (int g = 0; rc == COG_OK && g < cog::kGroups; ++g) {
+      if (!row[2 * g]) continue;
+      const float mean = (float)((double)row[2 * g + 1] / 65536.0 / (double)row[2 * g]);
+      v.var[g] = mean < h->p.var_min ? h->p.var_min : mean;
+    }
+  }
+  if (rc == COG_OK) {
+    check(cog::launch_share_set(h->buf.rga, pl.RG, pl.C, P, m, v, st), "sharing launch");
+    check(hipStreamSynchronize(st), "sharing");
+  }
+  (void)hipStreamSynchronize(st);
+  if (dmap) (void)hipFree(dmap);
+  (void)hipFree(part);
+  if (rc == COG_OK && gvar_out)
+    for (int g = 0; g < cog::kGroups; ++g) gvar_out[g] = v.var[g];
+  return rc;
 }
 
 cog_status cog_group_background(cog_ctx *h, uint8_t *map_out, int32_t map_on_device,

@@ -147,6 +147,17 @@ hipError_t launch_stats_table(const StatJob *jobs, int n, int max_blocks, int ma
 // Grouping: per-block {min, max, sum} of both keys ([blocks][6] u64), one
 // assignment pass (asg in/out, [blocks][kGroupStat] u64), and the final map.
 int group_blocks(int64_t P);
+// One shared variance per group: per-block rows {count, sum} x 3 and an
+// invalid-input count ([blocks][7] u64, reduced with launch_part_reduce),
+// then the stores of the members' shared variances (sign bit set) and of
+// the other pixels' own (map == nullptr: every pixel ungrouped).
+struct ShareVars {
+  float var[kGroups];
+};
+hipError_t launch_share_sum(const float *rga, int rg, int c, int64_t P, const uint8_t *map,
+                            uint64_t *part, hipStream_t s);
+hipError_t launch_share_set(float *rga, int rg, int c, int64_t P, const uint8_t *map,
+                            const ShareVars &v, hipStream_t s);
 hipError_t launch_group_range(const uint2 *keys, int64_t P, uint64_t *part, hipStream_t s);
 hipError_t launch_group_assign(const uint2 *keys, int64_t P, const GroupCenters &c, uint8_t *asg,
                                uint64_t *part, hipStream_t s);

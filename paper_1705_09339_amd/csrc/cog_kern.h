@@ -562,6 +562,15 @@ __device__ __forceinline__ uint32_t var_key(float S, float Q, float n) {
   return __float_as_uint(var) >> 16;
 }
 
+// One shared parameter set per group (§2 "Clustering Similar Background"):
+// the stored running-average variance carries the pixel's group flag in its
+// sign bit.  When set, the magnitude is the group's shared variance, which
+// the pixel uses and never adapts.  Every use takes the magnitude (a free
+// source modifier); an update keeps a shared value as it is.
+__device__ __forceinline__ bool rvar_shared(float stored) {
+  return (int32_t)__float_as_uint(stored) < 0;
+}
+
 // Warm-up of the plain mixture baseline: one thread per pixel steps its
 // mixture over the N training frames and stores it in the grouped layout.
 template <int C, int K, bool F32>
@@ -853,7 +862,7 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
             const float d = x[j][c] - rmu[j][c];
             dr2 = dr2 + d * d;
           }
-          if (rga_on && dr2 <= kp.lam_r2 * rvar[j]) {
+          if (rga_on && dr2 <= kp.lam_r2 * fabsf(rvar[j])) {
             st[j] = 1;  // S1: background, the running average adapts
             lab[j] = false;
 #pragma unroll
@@ -865,8 +874,8 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
               const float e = x[j][c] - rmu[j][c];
               sr = sr + e * e;
             }
-            const float v = kp.one_m_alpha_rga * rvar[j] + kp.alpha_rga * sr;
-            rvar[j] = v < kp.var_min ? kp.var_min : v;
+            const float v = kp.one_m_alpha_rga * fabsf(rvar[j]) + kp.alpha_rga * sr;
+            if (!rvar_shared(rvar[j])) rvar[j] = v < kp.var_min ? kp.var_min : v;
             dirty[j] = true;
           } else {
             surv[j] = true;
@@ -874,7 +883,7 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
             for (int c = 0; c < C; ++c) s_x[li * C + c] = x[j][c];
             s_dl[li] = dl;
             s_dr2[li] = dr2;
-            s_var[li] = rvar[j];
+            s_var[li] = fabsf(rvar[j]);
           }
         }
       }
@@ -997,7 +1006,7 @@ __global__ __launch_bounds__(kNT) void k_cascade(Buffers b, Frames fr, KParams k
         if (r & 2) {
 #pragma unroll
           for (int c = 0; c < C; ++c) rmu[j][c] = s_rg[li * (C + 1) + c];
-          rvar[j] = s_rg[li * (C + 1) + C];
+          if (!rvar_shared(rvar[j])) rvar[j] = s_rg[li * (C + 1) + C];
           dirty[j] = true;
         }
       }
@@ -1165,7 +1174,7 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
             const float d = x[j][c] - rmu[j][c];
             dr2 = dr2 + d * d;
           }
-          if (rga_on && dr2 <= kp.lam_r2 * rvar[j]) {
+          if (rga_on && dr2 <= kp.lam_r2 * fabsf(rvar[j])) {
             st[j] = 1;
             lab[j] = false;
 #pragma unroll
@@ -1177,8 +1186,8 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
               const float e = x[j][c] - rmu[j][c];
               sr = sr + e * e;
             }
-            const float v = kp.one_m_alpha_rga * rvar[j] + kp.alpha_rga * sr;
-            rvar[j] = v < kp.var_min ? kp.var_min : v;
+            const float v = kp.one_m_alpha_rga * fabsf(rvar[j]) + kp.alpha_rga * sr;
+            if (!rvar_shared(rvar[j])) rvar[j] = v < kp.var_min ? kp.var_min : v;
             dirty[j] = true;
           } else {
             surv[j] = true;
@@ -1186,7 +1195,7 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
             for (int c = 0; c < C; ++c) s_x[li * C + c] = x[j][c];
             s_dl[li] = dl;
             s_dr2[li] = dr2;
-            s_var[li] = rvar[j];
+            s_var[li] = fabsf(rvar[j]);
           }
         }
       }
@@ -1281,7 +1290,7 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
         if (r & 2) {
 #pragma unroll
           for (int c = 0; c < C; ++c) rmu[j][c] = s_rg[li * (C + 1) + c];
-          rvar[j] = s_rg[li * (C + 1) + C];
+          if (!rvar_shared(rvar[j])) rvar[j] = s_rg[li * (C + 1) + C];
           dirty[j] = true;
         }
       }
@@ -1478,12 +1487,12 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
             dr2 = dr2 + d * d;
           }
           const bool s0 = fd_on && fd_ok;
-          const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * rvar;
+          const bool s1 = !s0 && rga_on && dr2 <= kp.lam_r2 * fabsf(rvar);
           if constexpr (SAMP) {
             // confident: decided by the frame difference, or by the running
             // average within samp_lambda standard deviations (its variance before
             // this frame's update)
-            const bool conf = s0 || (s1 && dr2 <= kp.lam_s2 * rvar);
+            const bool conf = s0 || (s1 && dr2 <= kp.lam_s2 * fabsf(rvar));
             const uint32_t nsat = conf ? (sat < 65535u ? sat + 1u : 65535u) : 0u;
             sat = valid ? nsat : sat;
           }
@@ -1497,14 +1506,14 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
               const float e = x[c] - nmu[c];
               sr = sr + e * e;
             }
-            const float nv = kp.one_m_alpha_rga * rvar + kp.alpha_rga * sr;
+            const float nv = kp.one_m_alpha_rga * fabsf(rvar) + kp.alpha_rga * sr;
             // u8 input keeps both operands positive and finite, where the
             // larger binary32 is the larger bit pattern
             const float nvar = F32 ? fmaxf(kp.var_min, nv)
                                    : __int_as_float(max(__float_as_int(kp.var_min), __float_as_int(nv)));
 #pragma unroll
             for (int c = 0; c < C; ++c) rmu[c] = s1 ? nmu[c] : rmu[c];
-            rvar = s1 ? nvar : rvar;
+            rvar = s1 && !rvar_shared(rvar) ? nvar : rvar;
           }
           dirty |= s1 ? 1u : 0u;
           lab = s1 ? 0u : lab;
@@ -1524,7 +1533,7 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
               float dl = 0.0f;
 #pragma unroll
               for (int c = 0; c < C; ++c) dl = fmaxf(dl, fabsf(x[c] - xq[c]));
-              conf = confidence<C, F32>(prec, x, dl, dr2, rvar, kp);
+              conf = confidence<C, F32>(prec, x, dl, dr2, fabsf(rvar), kp);
               accept = conf >= kp.conf_thr;
             }
             if (accept) {
@@ -1552,7 +1561,7 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
                     for (int c = 0; c < C; ++c) rmu[c] = m.mu[kk][c];
                   }
                 }
-                rvar = sv;
+                rvar = rvar_shared(rvar) ? rvar : sv;
                 dirty = 1u;
               }
             }
@@ -1778,7 +1787,7 @@ __device__ __forceinline__ void frame_tile(const Buffers &b, const Frames &fr, c
     }
     dr2[j] = d2;
     s0[j] = valid[j] && fd_on && fd_ok;
-    s1[j] = valid[j] && !s0[j] && rga_on && d2 <= kp.lam_r2 * rvar[j];
+    s1[j] = valid[j] && !s0[j] && rga_on && d2 <= kp.lam_r2 * fabsf(rvar[j]);
     surv[j] = valid[j] && !s0[j] && !s1[j];
     if (s1[j]) lab4 &= ~(1u << j);
   }
@@ -1806,9 +1815,10 @@ __device__ __forceinline__ void frame_tile(const Buffers &b, const Frames &fr, c
         const float e = x[j][c] - nmu[c];
         sr = sr + e * e;
       }
-      const float nv = kp.one_m_alpha_rga * rvar[j] + kp.alpha_rga * sr;
-      const float nvar = F32 ? fmaxf(kp.var_min, nv)
-                             : __int_as_float(max(__float_as_int(kp.var_min), __float_as_int(nv)));
+      const float nv = kp.one_m_alpha_rga * fabsf(rvar[j]) + kp.alpha_rga * sr;
+      float nvar = F32 ? fmaxf(kp.var_min, nv)
+                       : __int_as_float(max(__float_as_int(kp.var_min), __float_as_int(nv)));
+      nvar = rvar_shared(rvar[j]) ? rvar[j] : nvar;
       float *rg = b.rga + (p0 + j) * RG;
       if constexpr (RG == 4) *reinterpret_cast<float4 *>(rg) = make_float4(nmu[0], nmu[1], nmu[2], nvar);
       else *reinterpret_cast<float2 *>(rg) = make_float2(nmu[0], nvar);
@@ -1864,7 +1874,8 @@ __device__ __forceinline__ void frame_tile(const Buffers &b, const Frames &fr, c
       float conf = 0.0f;
       bool accept = false;
       if (kde_on) {
-        conf = confidence<C, F32>(b.prior + p * PB, xs, lds.dl[i], lds.dr2[i], lds.var[i], kp);
+        conf = confidence<C, F32>(b.prior + p * PB, xs, lds.dl[i], lds.dr2[i], fabsf(lds.var[i]),
+                                  kp);
         accept = conf >= kp.conf_thr;
       }
       uint32_t res;
@@ -1890,6 +1901,7 @@ __device__ __forceinline__ void frame_tile(const Buffers &b, const Frames &fr, c
               for (int c = 0; c < C; ++c) sm[c] = m.mu[kk][c];
             }
           }
+          sv = rvar_shared(lds.var[i]) ? lds.var[i] : sv;
           float *rg = b.rga + p * RG;
           if constexpr (RG == 4) *reinterpret_cast<float4 *>(rg) = make_float4(sm[0], sm[1], sm[2], sv);
           else *reinterpret_cast<float2 *>(rg) = make_float2(sm[0], sv);

@@ -232,6 +232,49 @@ __global__ __launch_bounds__(kNT) void k_part_reduce(const uint64_t *part, int n
   }
 }
 
+// One shared parameter set per group (§2 "Clustering Similar Background",
+// the list's last item and eq. 3).  Per-block rows {count, sum} of each group
+// and a flag of invalid input, [blocks][7] u64: a member's variance (the
+// magnitude of the stored value) enters as rint(v * 2^16) in binary64, an
+// exact integer below 2^53, so the sums are exact and order-independent.
+__global__ __launch_bounds__(kNT) void k_share_sum(const float *rga, int rg, int c, int64_t P,
+                                                   const uint8_t *map, uint64_t *part) {
+  __shared__ uint64_t red[kNW];
+  const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  int g = 255;
+  uint64_t q = 0, bad = 0;
+  if (p < P) {
+    g = map[p];
+    if (g != 255) {
+      const double v = rint((double)fabsf(rga[p * rg + c]) * 65536.0);
+      if (g >= kGroups || !(v >= 0.0 && v < 9007199254740992.0)) bad = 1;
+      else q = (uint64_t)v;
+    }
+  }
+  uint64_t out[2 * kGroups + 1];
+#pragma unroll
+  for (int k = 0; k < kGroups; ++k) {
+    const bool in = g == k && !bad;
+    out[2 * k] = block_sum_u64(in ? 1ull : 0ull, red);
+    out[2 * k + 1] = block_sum_u64(in ? q : 0ull, red);
+  }
+  out[2 * kGroups] = block_sum_u64(bad, red);
+  if (threadIdx.x < 2 * kGroups + 1)
+    part[(int64_t)blockIdx.x * (2 * kGroups + 1) + threadIdx.x] = out[threadIdx.x];
+}
+
+// Members take their group's shared variance, stored with the sign bit set
+// (the cascade then uses it and never adapts it); every other pixel keeps the
+// magnitude of its variance as its own (map == nullptr: every pixel).
+__global__ __launch_bounds__(kNT) void k_share_set(float *rga, int rg, int c, int64_t P,
+                                                   const uint8_t *map, ShareVars v) {
+  const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (p >= P) return;
+  const int g = map ? map[p] : 255;
+  float *f = rga + p * rg + c;
+  *f = g < kGroups ? __uint_as_float(__float_as_uint(v.var[g]) | 0x80000000u) : fabsf(*f);
+}
+
 __global__ __launch_bounds__(kNT) void k_fill_u8(uint8_t *p, int64_t n, uint8_t v) {
   for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT)
     p[i] = v;
@@ -356,6 +399,18 @@ hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
   int64_t blocks = (n + kNT - 1) / kNT;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)blocks), dim3(kNT), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_share_sum(const float *rga, int rg, int c, int64_t P, const uint8_t *map,
+                            uint64_t *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_share_sum, dim3(group_blocks(P)), dim3(kNT), 0, s, rga, rg, c, P, map, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_share_set(float *rga, int rg, int c, int64_t P, const uint8_t *map,
+                            const ShareVars &v, hipStream_t s) {
+  hipLaunchKernelGGL(k_share_set, dim3(group_blocks(P)), dim3(kNT), 0, s, rga, rg, c, P, map, v);
   return hipGetLastError();
 }
 

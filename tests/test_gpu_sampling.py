@@ -105,7 +105,7 @@ def test_sampling_resume_through_export(C):
     a.step_frames(dev[20:80])
     blob = a.export_state()
     st = canon.parse(blob)
-    assert st["version"] == 2 and (st["sat"] > 0).any()
+    assert st["version"] == 3 and (st["sat"] > 0).any()
     b = C.CogStream(p, stream=torch.cuda.current_stream())
     b.import_state(blob)
     ma = torch.zeros((60, 64 * 40), dtype=torch.uint8, device="cuda")
