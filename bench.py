@@ -618,6 +618,34 @@ def main():
         res["grouping"] = {"ms": r(g_ms, 3), "iterations": ginfo["iterations"],
                            "grouped_frac": r(sum(g["grouped"] for g in ginfo["groups"]) / P, 4),
                            "cluster_sizes": [g["count"] for g in ginfo["groups"]]}
+        # one shared running-average variance per group: the fit, then the
+        # cascade frames from the shared state (median of 3 launches, each
+        # after its own training, grouping and sharing, which are untimed)
+        R.job(cog)
+        plain = R.masks.clone()
+        shared_ms, sh_fit = [], []
+        for _ in range(3):
+            cog.reset()
+            cog.train_prior(R.dev[:N])
+            cog.group(gmap)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            gv = cog.share(gmap)
+            sh_fit.append((time.perf_counter() - ts) * 1e3)
+            e0, e1 = R.ev(), R.ev()
+            e0.record(R.stream)
+            cog.step_frames(R.dev[N:], R.masks)
+            e1.record(R.stream)
+            torch.cuda.synchronize()
+            shared_ms.append(e0.elapsed_time(e1))
+        shared_ms.sort()
+        res["grouping"]["shared"] = {
+            "fit_ms": r(sorted(sh_fit)[1], 3), "shared_variances": [r(float(v), 3) for v in gv],
+            "frames_ms": r(shared_ms[1]), "frames_ms_unshared": r(s_cog["frames_ms"]),
+            "online_mpx_s": r(P * F / (shared_ms[1] * 1e-3) / 1e6, 1),
+            "mask_diff_vs_unshared": r(float((R.masks != plain).float().mean()), 5),
+            "accuracy": accuracy(R.masks, x["gt"][N:]),
+            "accuracy_unshared": accuracy(plain, x["gt"][N:])}
         log(f"grouping: {res['grouping']}")
     if x["acc"]:
         res["accuracy_vs_ground_truth"] = x["acc"]
