@@ -256,3 +256,76 @@ def test_shared_stream_in_batched_ticks(C, per_tick):
         u.close()
         o.close()
         ou.close()
+
+
+def _share_run(C, p, fr, N, mode):
+    """Train, group and share on the GPU and in the oracle (the GPU's map, which
+    must equal the oracle's), then step; masks, level counts and state exactly."""
+    import torch
+    dev = torch.from_numpy(np.ascontiguousarray(fr)).cuda()
+    P, T = p.width * p.height, len(fr)
+    s = C.CogStream(p, stream=torch.cuda.current_stream())
+    o = O.Oracle(orc_params_like(p))
+    try:
+        s.train_prior(dev[:N])
+        m = np.zeros(P, dtype=np.uint8)
+        s.group(m)
+        o.train(fr[:N])
+        mo, _ = o.group()
+        assert np.array_equal(m, mo)
+        assert (m != 255).any()
+        gv, go = s.share(m), o.group_share(mo)
+        assert np.array_equal(gv.view(np.uint32), go.view(np.uint32))
+        masks = torch.zeros((T - N, P), dtype=torch.uint8, device="cuda")
+        ig = []
+        for t0 in range(N, T, mode):
+            t1 = min(T, t0 + mode)
+            ig.extend(s.step_frames(dev[t0:t1], masks[t0 - N:t1 - N], want_info=True))
+        torch.cuda.synchronize()
+        mg = masks.cpu().numpy()
+        for t in range(N, T):
+            mo_t, io = o.step(fr[t])
+            assert np.array_equal(mg[t - N], mo_t), t
+            assert dict(ig[t - N]) == io, (t, dict(ig[t - N]), io)
+        _same_state(canon.parse(s.export_state()), canon.parse(o.export()))
+        return ig
+    finally:
+        s.close()
+        o.close()
+
+
+@pytest.mark.parametrize("mode", [1, 9])
+def test_shared_with_sampling(C, mode):
+    """Sharing under confidence-based sampling: the sampling gate takes the
+    shared variance too, and halted blocks keep it."""
+    spec = synth.preset("surveil-160x120-k3").with_(frames=160, n_train=50,
+                                                    seed=synth.video.BASE_SEED + 931)
+    fr = synth.make_stream(spec)
+    p = gpu_params(C, 160, 120, K=3, stage_mask=7 | 8, samp_window=8, samp_period=4)
+    say("share + sampling, mode", mode)
+    ig = _share_run(C, p, fr, 50, mode)
+    assert sum(i["n_skip"] for i in ig) > 0
+
+
+def test_shared_f32_single_channel(C):
+    """f32 input, one channel (latent maps flattened to pixels), K = 3."""
+    rng = np.random.default_rng(170509345)
+    T, N, H, W = 60, 20, 96, 40
+    base = rng.normal(0, 1, size=(H, W, 1)).astype(np.float32)
+    noise = rng.uniform(0.02, 0.3, size=(H, W, 1)).astype(np.float32)
+    fr = np.stack([base + noise * rng.normal(0, 1, size=(H, W, 1)).astype(np.float32)
+                   for _ in range(T)])
+    fr[35:, 30:60, 5:15] += 2.5
+    p = gpu_params(C, W, H, c=1, K=3, dtype=C.COG_F32, in_lo=-4.0, in_hi=4.0,
+                   var_init=0.25, var_min=0.0025, res_e1=0.2, res_e2=0.6, tau_fd=0.0)
+    say("share + f32 C=1")
+    _share_run(C, p, fr, N, 13)
+
+
+def test_shared_u8_single_channel_k2(C):
+    spec = synth.preset("surveil-160x120-k3").with_(width=96, height=64, frames=90, n_train=30,
+                                                    seed=synth.video.BASE_SEED + 932)
+    fr = np.ascontiguousarray(synth.make_stream(spec)[..., :1])
+    p = gpu_params(C, 96, 64, c=1, K=2)
+    say("share + u8 C=1 K=2")
+    _share_run(C, p, fr, 30, 60)
