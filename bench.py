@@ -45,7 +45,11 @@ HBM_PEAK_GBS = 8000.0
 # SIMD would be half of it; the cascade's and the mixture's launches issue
 # VALU instructions faster than that, by their SQ counters.)
 ALU_PEAK_GOPS = 256 * 4 * 32 * 2.4
-LEGS = ("stream", "infos", "per_frame", "model", "sweep", "sampling", "grouping", "batch", "serve")
+LEGS = ("stream", "infos", "per_frame", "model", "sweep", "small", "sampling", "grouping", "batch",
+        "serve")
+# the two smaller configurations: their state fits the 256 MB last-level cache, so
+# they are reported labelled cache-resident and carry no roofline claim
+SMALL = ("surveil-160x120-k3", "surveil-640x480-k5")
 GEN_THREADS = 16
 
 
@@ -523,6 +527,7 @@ def main():
     if tr:
         hbm["traffic"] = int(float(tr["hbm_bytes_per_launch"]))
         hbm["traffic_gbs"] = r(hbm["traffic"] / launch_s / 1e9, 1)
+        hbm["amplification"] = r(hbm["traffic"] / b_stream, 3)  # counter bytes / algorithmic
     vl = profile_sq(spec.name, kname, grid)
     dominant = "cascade" if s_cog["frames_ms"] >= s_cog["train_ms"] else "train"
     if dominant == "cascade" and vl and "SQ_INSTS_VALU" in vl:
@@ -565,6 +570,7 @@ def main():
             pfr["traffic_per_frame"] = int(float(tpf["hbm_bytes_per_launch"]))
             pfr["traffic_gbs"] = r(pfr["traffic_per_frame"] / (us * 1e-6) / 1e9, 1)
             pfr["traffic_frac"] = r(pfr["traffic_gbs"] / HBM_PEAK_GBS, 4)
+            pfr["amplification"] = r(pfr["traffic_per_frame"] / (bpx * P), 3)
             pfr["kernel"] = tpf.get("kernel", pfr["kernel"])
         gb = 3 + 1 + 2 * K * 5 * 4
         gus = res["per_frame"]["gmm"]["us_per_frame"]
@@ -679,6 +685,27 @@ def main():
             torch.cuda.empty_cache()
             log(f"sweep {name}: {sweep[name]}")
         res["occupancy_sweep"] = sweep
+
+    if "small" in legs:
+        small = {}
+        for name in SMALL:
+            sw, sx = one_workload(args, C, torch, synth.preset(name), legs & {"per_frame"},
+                                  headline=False)
+            small[name] = {k: sw[k] for k in ("early_rejection", "value", "speedup_vs_gmm", "online",
+                                              "train_ms", "frames_ms")}
+            small[name]["gmm_value"] = sw["gmm"]["value"]
+            if "per_frame" in sw:
+                small[name]["per_frame_us"] = {"cog": sw["per_frame"]["cog"]["us_per_frame"],
+                                               "gmm": sw["per_frame"]["gmm"]["us_per_frame"]}
+            sp = sx["R"].params(C.COG_PATH_CASCADE)
+            small[name]["state_mb"] = r(C.cog_state_bytes(sp) / 1e6, 1)
+            small[name]["cache_resident"] = True
+            sx["cog"].close()
+            sx["gmm"].close()
+            del sx
+            torch.cuda.empty_cache()
+            log(f"small {name}: {small[name]}")
+        res["small_configs"] = small
 
     if "batch" in legs:
         torch.cuda.empty_cache()
@@ -1038,12 +1065,15 @@ def cpu_baseline(frames, spec, budget_s):
         idx = np.arange(0, P, stride)
         return np.ascontiguousarray(flat[:, idx][:, None])
 
-    def run_one(sub):
+    def run_one(sub, gmm=False):
         orc = O.Oracle(O.make_params(sub.shape[2], 1, 3, K))
         ts = time.perf_counter()
         orc.train(sub[:N])
         for t in range(N, T):
-            orc.step(sub[t])
+            if gmm:
+                orc.gmm_step(sub[t])
+            else:
+                orc.step(sub[t])
         el = time.perf_counter() - ts
         orc.close()
         return el
@@ -1066,13 +1096,17 @@ def cpu_baseline(frames, spec, budget_s):
     ela = time.perf_counter() - ts
     log(f"cpu oracle: 1 thread {n1} px x {T} frames in {el1:.1f} s; {nthr} threads {na} px in {ela:.1f} s")
     one = {"value": r(n1 * F / el1 / 1e6, 3), "cores": 1, "seconds": r(el1, 2), "pixels": n1}
+    # the oracle's plain mixture (the comparator) on the same one-thread sample
+    elg = run_one(sub, gmm=True)
+    one_gmm = {"value": r(n1 * F / elg / 1e6, 3), "cores": 1, "seconds": r(elg, 2), "pixels": n1,
+               "cog_speedup": r(elg / el1, 3)}
     return {"value": r(na * F / ela / 1e6, 3), "unit": "Mpixel-frames/s", "cores": nthr,
             "kind": "oracle",
             "sample": f"every {stride_all}th pixel ({na} px) of all {T} frames of {spec.name}: "
                       f"training over {N}, cascade over {F}; value counts the {F} classified "
                       f"frames per second of training + cascade, like the GPU value",
             "seconds": r(ela, 2), "host": host, "host_cores": ncpu,
-            "single_core": one}
+            "single_core": one, "single_core_gmm": one_gmm}
 
 
 if __name__ == "__main__":

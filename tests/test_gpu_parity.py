@@ -43,6 +43,19 @@ def test_train_parity_160x120(C):
     assert nb == 0, f"{nb} floats differ in their bits"
 
 
+@pytest.mark.parametrize("h", [2.0, 8.0, 14.0, 24.0, 64.0])
+def test_train_parity_kernel_bandwidths(C, h):
+    """Kernel bandwidths from narrow (a level's weight in one or two bins) to
+    wide (weights over every bin): the prior tables, counts and the whole
+    state equal the oracle's."""
+    fr = small_stream()
+    p = gpu_params(C, 160, 120, K=3, kde_h=h)
+    say("train 160x120 K=3 N=50, kde_h", h)
+    _, _, sg = run_gpu(C, p, fr[:51], 50, mode="step", infos=False)
+    _, _, so = run_orc(orc_params_like(p), fr[:51], 50)
+    assert compare_state(sg, so) == 0
+
+
 # ------------------------------------------------------------------ cascade
 
 def test_cascade_per_frame_parity_160x120(C):
