@@ -117,13 +117,20 @@ def train_bytes(P, N, K, C=3):
 # ---- committed counter summaries ---------------------------------------------------
 
 def kernel_source_hash() -> str:
+    """Hash of the device sources' code: comments and blank lines are left out,
+    so a comment edit keeps the committed counters valid."""
     import hashlib
+    import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1705_09339_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".h")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(d, f), encoding="utf-8") as fh:
+                text = fh.read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+            h.update(code.encode())
     return h.hexdigest()[:16]
 
 

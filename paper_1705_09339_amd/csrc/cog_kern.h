@@ -1340,10 +1340,11 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
 // dense lists instead.)
 //  - dense state (previous value, label, running average) in registers for
 //    the whole launch;
-//  - a pixel's mixture record is read from HBM the first time the pixel
-//    reaches S3 in the launch (the load is issued before S2 runs) and then
-//    stays in registers -- only this lane ever touches it -- and is written
-//    back once at the end of the launch;
+//  - a pixel's mixture record is read from HBM when the launch starts (launches
+//    of kEagerRecordFrames frames or more) or the first time the pixel
+//    reaches S3 (the load is issued before S2 runs), and then stays in
+//    registers -- only this lane ever touches it -- and is written back once
+//    at the end of the launch;
 //  - the input is block-staged through LDS (InStage): the global-memory wait
 //    is paid once per block of frames, on loads issued a block earlier;
 //  - frames go two per loop iteration, the input alternating between two
@@ -1351,6 +1352,10 @@ __global__ __launch_bounds__(64) void k_cascade_w(Buffers b, Frames fr, KParams 
 //  - the mask and statistics stores are bounds-checked buffer stores;
 //  - for u8 input up to K = 5 the register budget keeps five waves per SIMD (a 640x480
 //    frame is 4.7 waves per SIMD: all of them stay resident).
+// Launches of at least this many frames load every pixel's mixture record at
+// their start (shorter ones when the pixel first reaches S3).
+constexpr int kEagerRecordFrames = 32;
+
 // LDS of one wave running cascade_tile: the tile's prior records (when
 // staged) and the input ring.
 template <int C, bool F32, bool LP>
@@ -1417,6 +1422,13 @@ __device__ __forceinline__ void cascade_tile(const Buffers &b, const Frames &fr,
                            : b.prior + pcl * PB;
   float *grec = b.gmm + pcl * R;
   Mix<C, K> m;  // the pixel's mixture, valid once have_rec
+  // A long launch requests every record at its start: most pixels reach S3
+  // at some frame of a long run, and a record first requested inside the
+  // frame loop stalls the whole wave on one memory round trip.
+  if (fr.nframes >= kEagerRecordFrames) {
+    if (valid) rec_load<C, K>(grec, m);
+    have_rec = 1u;
+  }
 
   // byte offset of the lane's pixel in a frame's mask, and of the lane's
   // statistics word in a frame's row; out-of-range lanes are dropped by the
