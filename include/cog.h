@@ -390,7 +390,11 @@ cog_status cog_server_create(void *hip_stream, size_t hbm_budget, int32_t max_st
 
 /* Admit a stream: reserve its state within the budget, create its context
  * (parameters as for cog_create; cascade path, 64-pixel tiles) and run its
- * training on n_train device frames.  *id receives the stream's id.
+ * training on n_train device frames.  *id receives the stream's id.  The
+ * training is enqueued on the server's side stream and the call returns
+ * before it ends: train_frames must stay valid until the training has ended,
+ * that is until the stream's first completion is reported or until
+ * cog_server_drain of the stream (or of all streams) returns.
  * COG_E_OOM when the state does not fit the budget or max_streams streams
  * are open; other errors as for cog_create and cog_train_prior. */
 cog_status cog_server_open(cog_server *s, const cog_params *p, const void *train_frames,
@@ -404,7 +408,8 @@ cog_status cog_server_submit(cog_server *s, int32_t id, const void *frames, int3
                              uint8_t *masks, int64_t tag);
 
 /* Close stream id: its queued frames still complete; then its state range
- * returns to the reservation.  COG_E_INVALID for an unknown id. */
+ * returns to the reservation (after the stream's training, if that is still
+ * running).  COG_E_INVALID for an unknown id. */
 cog_status cog_server_close(cog_server *s, int32_t id);
 
 /* Move up to max completions (oldest first) to out; *n receives the count.
@@ -413,7 +418,7 @@ cog_status cog_server_poll(cog_server *s, cog_completion *out, int32_t max, int3
                            int64_t wait_us);
 
 /* Wait until every submitted frame (of stream id, or of all streams if
- * id < 0) has completed. */
+ * id < 0) has completed and the training of those streams has ended. */
 cog_status cog_server_drain(cog_server *s, int32_t id);
 
 /* Canonical state of stream id (see cog_export_state), after its submitted

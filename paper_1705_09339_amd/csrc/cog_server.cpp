@@ -151,7 +151,12 @@ void finalize(cog_server *s, int32_t id) {
   auto it = s->streams.find(id);
   if (it == s->streams.end()) return;
   SStream &st = it->second;
-  if (st.trained) (void)hipEventDestroy(st.trained);
+  if (st.trained) {
+    // the training may still write the stream's state (a stream closed
+    // before its training ended): wait for it before the range is reused
+    (void)hipEventSynchronize(st.trained);
+    (void)hipEventDestroy(st.trained);
+  }
   if (st.ctx->own_state || st.ctx->stage_in || st.ctx->stage_mask)
     cog_destroy(st.ctx);
   else
@@ -518,6 +523,12 @@ cog_status cog_server_drain(cog_server *s, int32_t id) {
   s->cv_work.notify_one();
   s->cv_done.wait(lk, [s, id] { return idle(s, id) || s->sticky != COG_OK; });
   if (s->sticky != COG_OK) return sfail(s->sticky, "server failed: " + s->sticky_msg);
+  // a stream with nothing submitted may still be training
+  for (auto &kv : s->streams) {
+    if (id >= 0 && kv.first != id) continue;
+    if (!trained(kv.second) && hipEventSynchronize(kv.second.trained) != hipSuccess)
+      return sfail(COG_E_DEVICE, "training failed");
+  }
   return COG_OK;
 }
 

@@ -349,3 +349,31 @@ def test_serving_4k_stream_sampled_against_oracle(C):
     mo, _, so = run_orc(orc_params_like(p1), fr1, 20)
     assert np.array_equal(m1, mo), int((m1 != mo).sum())
     assert compare_state(canon.parse(states[1]), so) == 0
+
+
+def test_drain_waits_for_training(C):
+    """A stream with nothing submitted: cog_server_drain returns after its
+    training, so the training frames may be overwritten then; its results still
+    equal the alone run's.  A stream closed while it may still train gives its
+    range back only after the training."""
+    import torch
+    fr = torch.from_numpy(_synth(64, 48, 40, 8)).cuda()
+    p = gpu_params(C, 64, 48, c=3, K=5)
+    ref_masks, ref_state = alone(C, p, fr, 20)
+    train = fr[:20].clone()
+    torch.cuda.synchronize()
+    srv = C.CogServer(hbm_budget=int(C.cog_state_bytes(p) * 1.5), max_streams=4)
+    gone = srv.open(p, train)
+    srv.close_stream(gone)          # its range returns after its training
+    sid = srv.open(p, train)        # and is reused here
+    srv.drain(sid)
+    train.zero_()                   # the training has read its frames
+    torch.cuda.synchronize()
+    masks = torch.zeros((20, 64 * 48), dtype=torch.uint8, device="cuda")
+    for k in range(20):
+        srv.submit(sid, fr[20 + k:21 + k], masks[k:k + 1], tag=k)
+    srv.drain(sid)
+    assert [c["tag"] for c in srv.poll()] == list(range(20))
+    assert np.array_equal(masks.cpu().numpy(), ref_masks)
+    assert srv.export_state(sid) == ref_state
+    srv.close()
