@@ -1018,6 +1018,25 @@ def serving_leg(args, C):
            "mpx_s": round(st["pixel_frames"] / wall / 1e6, 1),
            "latency_p50_ms": round(pct(lat, 50), 3), "latency_p99_ms": round(pct(lat, 99), 3),
            "latency_max_ms": round(float(lat.max()), 3)}
+    # where the tail is: a stream's first frame (it may wait for the stream's
+    # training) against its later frames, and the later frames per frame size
+    first = np.zeros(len(comps), dtype=bool)
+    seen = set()
+    for i, c in enumerate(comps):
+        if c["stream_id"] not in seen:
+            seen.add(c["stream_id"])
+            first[i] = True
+    split = {"first_frame": {"n": int(first.sum()), "p50_ms": round(pct(lat[first], 50), 3),
+                             "p99_ms": round(pct(lat[first], 99), 3)},
+             "later_frames": {"n": int((~first).sum()), "p50_ms": round(pct(lat[~first], 50), 3),
+                              "p99_ms": round(pct(lat[~first], 99), 3),
+                              "max_ms": round(float(lat[~first].max()), 3)}}
+    size_of = np.array([sizes[reqs[c["tag"]]["si"]][0] for c in comps])
+    for w, h in sizes:
+        sel = (size_of == w) & ~first
+        if sel.any():
+            split[f"later_{w}x{h}"] = {"n": int(sel.sum()), "p99_ms": round(pct(lat[sel], 99), 3)}
+    res["latency_split"] = split
     log(f"serve: {res}")
     return res
 

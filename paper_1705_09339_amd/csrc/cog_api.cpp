@@ -585,20 +585,38 @@ cog_status cog_train_prior(cog_ctx *h, const void *frames, int32_t n, int32_t fr
     if (e != hipSuccess) return hip_fail(h, e, "frame upload");
     dfr = h->stage_in;
   }
+  cog_status s = cog_rt::train_range(h, dfr, n, 0, pl.P, h->stream);
+  if (s != COG_OK) return s;
+  if (!frames_on_device) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "training");
+  }
+  cog_rt::train_finish(h, n);
+  return COG_OK;
+}
+
+extern "C++" {
+namespace cog_rt {
+
+cog_status train_range(cog_ctx *h, const void *dframes, int n, int64_t p0, int64_t p1,
+                       hipStream_t st) {
+  const Plan &pl = h->plan;
   const cog::KParams kp = make_kparams(&h->p, n);
   const bool cascade = h->p.path == COG_PATH_CASCADE;
   hipError_t e = cog::launch_train(pl.C, pl.K, h->p.dtype == COG_F32, cascade, cascade, h->buf,
-                                   dfr, (int64_t)pl.P * pl.C, n, kp, h->stream);
+                                   dframes, (int64_t)pl.P * pl.C, n, kp, p0, p1, st);
   if (e != hipSuccess) return hip_fail(h, e, "training launch");
-  if (!frames_on_device) {
-    e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "training");
-  }
-  h->kp = kp;
-  h->n_train = n;
-  h->frame = n;
   return COG_OK;
 }
+
+void train_finish(cog_ctx *h, int n) {
+  h->kp = make_kparams(&h->p, n);
+  h->n_train = n;
+  h->frame = n;
+}
+
+}  // namespace cog_rt
+}  // extern "C++"
 
 cog_status cog_step_frames(cog_ctx *h, const void *frames, int32_t n, int32_t frames_on_device,
                            uint8_t *masks_out, int32_t masks_on_device, cog_step_info *infos) {

@@ -43,6 +43,14 @@ struct Plan {
 cog_status fail(cog_ctx *h, cog_status s, const std::string &msg);
 cog_status hip_fail(cog_ctx *h, hipError_t e, const char *what);
 
+// Training of the pixels [p0, p1) on stream st (device frames; p0 a multiple
+// of 128), and the context's switch to trained once every pixel has been
+// trained: together they are cog_train_prior, which the serving loop issues
+// in slices between its ticks.
+cog_status train_range(cog_ctx *h, const void *dframes, int n, int64_t p0, int64_t p1,
+                       hipStream_t st);
+void train_finish(cog_ctx *h, int n);
+
 // Per-frame statistics from the reduced counter blocks [n][nblk][kStat].
 void fill_infos(const cog_ctx *h, int64_t first_frame, int n, const uint32_t *blocks,
                 cog_step_info *infos, int nblk);

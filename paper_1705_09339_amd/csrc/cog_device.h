@@ -114,9 +114,12 @@ struct GroupBands {
 };
 
 // Launchers (cog_kernels.hip).  Return hipSuccess or the launch error.
+// Training of the pixels [p0, p1) (the frames hold every pixel; slices of a
+// stream start at multiples of 128 pixels, so each label word is written by
+// one launch).
 hipError_t launch_train(int C, int K, bool f32in, bool prior, bool aos, const Buffers &b,
                         const void *frames, int64_t stride, int n, const KParams &kp,
-                        hipStream_t s);
+                        int64_t p0, int64_t p1, hipStream_t s);
 hipError_t launch_cascade(int C, int K, bool f32in, int tile, const Buffers &b, const Frames &fr,
                           const KParams &kp, hipStream_t s);
 hipError_t launch_gmm(int C, int K, bool f32in, const Buffers &b, const Frames &fr,
@@ -190,7 +193,8 @@ int tick_blocks_per_cu(int C, int K, bool f32in, bool lp, bool samp);
 // K = 1..8, one translation unit each; the calls above dispatch on K.
 template <int K>
 hipError_t launch_train_k(int C, bool f32in, bool prior, const Buffers &b, const void *frames,
-                          int64_t stride, int n, const KParams &kp, hipStream_t s);
+                          int64_t stride, int n, const KParams &kp, int64_t p0, int64_t p1,
+                          hipStream_t s);
 template <int K>
 hipError_t launch_cascade_k(int C, bool f32in, int tile, const Buffers &b, const Frames &fr,
                             const KParams &kp, hipStream_t s);

@@ -575,10 +575,10 @@ __device__ __forceinline__ bool rvar_shared(float stored) {
 // mixture over the N training frames and stores it in the grouped layout.
 template <int C, int K, bool F32>
 __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, int64_t stride,
-                                               int n, KParams kp) {
+                                               int n, KParams kp, int64_t p0, int64_t p1) {
   const int lane = threadIdx.x & 63;
-  const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
-  const bool valid = p < b.P;
+  const int64_t p = p0 + (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const bool valid = p < p1;
   bool lab = false;
   if (valid) {
     float x[C], xp[C], xn[C];
@@ -622,7 +622,8 @@ constexpr int kTrainPx = 128;
 
 template <int C, int K, bool F32>
 __global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const void *frames,
-                                                        int64_t stride, int n, KParams kp) {
+                                                        int64_t stride, int n, KParams kp,
+                                                        int64_t p0, int64_t p1) {
   __shared__ uint4 s_w[256 * kBins * 2 / 16];
   for (int i = threadIdx.x; i < 256 * kBins * 2 / 16; i += 2 * kTrainPx)
     s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
@@ -631,8 +632,8 @@ __global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const v
   const bool prior_role = threadIdx.x < kTrainPx;  // wave-uniform
   const int t = prior_role ? threadIdx.x : threadIdx.x - kTrainPx;
   const int lane = t & 63;
-  const int64_t p = (int64_t)blockIdx.x * kTrainPx + t;
-  const bool valid = p < b.P;
+  const int64_t p = p0 + (int64_t)blockIdx.x * kTrainPx + t;
+  const bool valid = p < p1;
   if (prior_role) {
     if (!valid) return;
     uint32_t acc[C][kBins];
@@ -2142,14 +2143,18 @@ inline unsigned grid_for(int64_t P, int tile) { return (unsigned)((P + tile - 1)
 
 template <int K>
 hipError_t launch_train_k(int C, bool f32in, bool prior, const Buffers &b, const void *frames,
-                          int64_t stride, int n, const KParams &kp, hipStream_t s) {
-  const unsigned g = grid_for(b.P, kNT);
+                          int64_t stride, int n, const KParams &kp, int64_t p0, int64_t p1,
+                          hipStream_t s) {
+  if (p1 <= p0) return hipSuccess;
+  const int64_t np = p1 - p0;
+  const unsigned g = grid_for(np, kNT);
 #define COG_TRAIN(CC, FF, _)                                                                   \
   if (prior)                                                                                   \
-    hipLaunchKernelGGL((k_train_prior<CC, K, FF>), dim3(grid_for(b.P, kTrainPx)),             \
-                       dim3(2 * kTrainPx), 0, s, b, frames, stride, n, kp);                    \
+    hipLaunchKernelGGL((k_train_prior<CC, K, FF>), dim3(grid_for(np, kTrainPx)),              \
+                       dim3(2 * kTrainPx), 0, s, b, frames, stride, n, kp, p0, p1);            \
   else                                                                                         \
-    hipLaunchKernelGGL((k_train<CC, K, FF>), dim3(g), dim3(kNT), 0, s, b, frames, stride, n, kp)
+    hipLaunchKernelGGL((k_train<CC, K, FF>), dim3(g), dim3(kNT), 0, s, b, frames, stride, n, kp, \
+                       p0, p1)
   COG_C_CASES(COG_TRAIN, 0)
 #undef COG_TRAIN
   return hipGetLastError();
@@ -2291,7 +2296,8 @@ hipError_t launch_gmm_k(int C, bool f32in, const Buffers &b, const Frames &fr, c
 // Explicit instantiation of every launcher for one K.
 #define COG_INSTANTIATE_K(KK)                                                                  \
   template hipError_t launch_train_k<KK>(int, bool, bool, const Buffers &, const void *,     \
-                                         int64_t, int, const KParams &, hipStream_t);          \
+                                         int64_t, int, const KParams &, int64_t, int64_t,      \
+                                         hipStream_t);                                         \
   template hipError_t launch_cascade_k<KK>(int, bool, int, const Buffers &, const Frames &,   \
                                            const KParams &, hipStream_t);                      \
   template hipError_t launch_frame_k<KK>(int, bool, const Buffers &, const Frames &,           \

@@ -302,9 +302,9 @@ static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
 
 hipError_t launch_train(int C, int K, bool f32in, bool prior, bool aos, const Buffers &b,
                         const void *frames, int64_t stride, int n, const KParams &kp,
-                        hipStream_t s) {
-  if (prior != aos) return hipErrorInvalidValue;
-#define CALL(KK) launch_train_k<KK>(C, f32in, prior, b, frames, stride, n, kp, s)
+                        int64_t p0, int64_t p1, hipStream_t s) {
+  if (prior != aos || p0 < 0 || p1 > b.P || (p0 & 127)) return hipErrorInvalidValue;
+#define CALL(KK) launch_train_k<KK>(C, f32in, prior, b, frames, stride, n, kp, p0, p1, s)
   COG_K_DISPATCH(CALL)
 #undef CALL
   return hipErrorInvalidValue;

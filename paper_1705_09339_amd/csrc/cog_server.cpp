@@ -1,10 +1,14 @@
 // Host runtime of the serving loop (include/cog.h, "Serving loop").
 //
 // Two threads per server: a scheduler that issues ticks and a completer that
-// waits for them.  All HIP work of a server (context creation, training,
-// ticks, exports) is enqueued on the server's stream while holding the
-// server mutex, so it is ordered; the completer releases the mutex while it
-// waits for the oldest tick in flight.
+// waits for them.  The HIP work of a server's streams (training, ticks,
+// exports) is enqueued on the server's stream while holding the server
+// mutex, so it is ordered; the completer releases the mutex while it waits
+// for the oldest tick in flight.  A new stream's training runs there too, in
+// slices of kSlicePixels pixels issued between ticks: a tick waits for at
+// most one slice, where one whole-stream training launch (several
+// milliseconds at 3840x2160) would hold every tick behind it or compete with
+// it for the compute units.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,10 +42,19 @@ struct SStream {
   size_t bytes = 0;
   int64_t pixels = 0;
   bool closing = false;
-  int in_flight = 0;  // submissions issued and not complete
-  hipEvent_t trained = nullptr;  // end of the training launch (until seen complete)
+  int in_flight = 0;         // submissions and training slices issued and not complete
+  int slices_in_flight = 0;  // of those, training slices
+  // training still to issue: slices cover the pixels [train_next, pixels)
+  bool training = false;
+  const void *train_frames = nullptr;
+  int32_t n_train = 0;
+  int64_t train_next = 0;
   std::deque<Submission> q;
 };
+
+// Pixels per training slice: about 0.2 ms of a 1920x1080 K=5 stream's
+// training (a multiple of 128, the training workgroup).
+constexpr int64_t kSlicePixels = 1 << 18;
 
 struct Issued {
   int32_t id;
@@ -54,6 +67,7 @@ struct Issued {
 struct Tick {
   hipEvent_t ev = nullptr;
   std::vector<Issued> work;
+  int32_t slice_of = -1;  // a training slice of this stream (no work)
   cog_status status = COG_OK;
 };
 
@@ -108,7 +122,8 @@ struct Arena {
 struct cog_server {
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  hipStream_t train_stream = nullptr;  // admissions train here, beside the ticks
+  hipStream_t train_stream = nullptr;  // admissions upload their weights here
+  std::deque<int32_t> train_q;         // streams with training slices to issue, in order
   int device = 0;
   size_t budget = 0, in_use = 0;
   int opening = 0;  // admissions reserved and not yet registered
@@ -151,12 +166,6 @@ void finalize(cog_server *s, int32_t id) {
   auto it = s->streams.find(id);
   if (it == s->streams.end()) return;
   SStream &st = it->second;
-  if (st.trained) {
-    // the training may still write the stream's state (a stream closed
-    // before its training ended): wait for it before the range is reused
-    (void)hipEventSynchronize(st.trained);
-    (void)hipEventDestroy(st.trained);
-  }
   if (st.ctx->own_state || st.ctx->stage_in || st.ctx->stage_mask)
     cog_destroy(st.ctx);
   else
@@ -190,20 +199,82 @@ void retire_front(cog_server *s, cog_status st) {
     if (it != s->streams.end()) {
       SStream &ss = it->second;
       ss.in_flight -= 1;
-      if (ss.closing && ss.q.empty() && ss.in_flight == 0) finalize(s, w.id);
+      if (ss.closing && ss.q.empty() && ss.in_flight == 0 && !ss.training) finalize(s, w.id);
+    }
+  }
+  if (t.slice_of >= 0) {
+    auto it = s->streams.find(t.slice_of);
+    if (it != s->streams.end()) {
+      SStream &ss = it->second;
+      ss.in_flight -= 1;
+      ss.slices_in_flight -= 1;
+      if (ss.closing && ss.q.empty() && ss.in_flight == 0 && !ss.training) finalize(s, t.slice_of);
     }
   }
   if (t.ev) s->spare_events.push_back(t.ev);
   s->cv_done.notify_all();
 }
 
-// Whether a stream's training has finished (its frames may join ticks).
-bool trained(SStream &st) {
-  if (!st.trained) return true;
-  if (hipEventQuery(st.trained) != hipSuccess) return false;
-  (void)hipEventDestroy(st.trained);
-  st.trained = nullptr;
-  return true;
+// Whether every slice of a stream's training has been issued: its frames
+// may join the next tick, which the server's stream runs after them.
+bool trained(const SStream &st) { return !st.training; }
+
+// An event recorded on the server's stream for a tick or a slice.
+hipEvent_t take_event(cog_server *s) {
+  hipEvent_t ev = nullptr;
+  if (s->spare_events.empty()) {
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      s->sticky = COG_E_DEVICE;
+      s->sticky_msg = "event creation failed";
+      return nullptr;
+    }
+  } else {
+    ev = s->spare_events.back();
+    s->spare_events.pop_back();
+  }
+  return ev;
+}
+
+// Issues the next training slice of the oldest stream still training.
+bool issue_slice(cog_server *s) {
+  while (!s->train_q.empty()) {
+    const int32_t id = s->train_q.front();
+    auto it = s->streams.find(id);
+    if (it == s->streams.end() || !it->second.training) {
+      s->train_q.pop_front();
+      continue;
+    }
+    SStream &st = it->second;
+    if (st.closing && st.q.empty()) {
+      // closed with nothing queued: the rest of its training is not needed
+      st.training = false;
+      s->train_q.pop_front();
+      if (st.in_flight == 0) finalize(s, id);
+      continue;
+    }
+    const int64_t p1 = std::min(st.pixels, st.train_next + kSlicePixels);
+    Tick t;
+    t.slice_of = id;
+    t.status = cog_rt::train_range(st.ctx, st.train_frames, st.n_train, st.train_next, p1, s->stream);
+    if (t.status != COG_OK) {
+      s->sticky = t.status;
+      s->sticky_msg = cog_last_error(st.ctx);
+    }
+    st.train_next = p1;
+    st.in_flight += 1;
+    st.slices_in_flight += 1;
+    if (p1 == st.pixels) {
+      cog_rt::train_finish(st.ctx, st.n_train);
+      st.training = false;
+      st.train_frames = nullptr;
+      s->train_q.pop_front();
+    }
+    t.ev = take_event(s);
+    if (t.ev && hipEventRecord(t.ev, s->stream) != hipSuccess) t.status = COG_E_DEVICE;
+    s->in_flight.push_back(std::move(t));
+    return true;
+  }
+  return false;
 }
 
 // Gathers the oldest submission of every stream into one tick and issues it.
@@ -233,16 +304,7 @@ bool issue_tick(cog_server *s) {
     st.q.pop_front();
     st.in_flight += 1;
   }
-  if (s->spare_events.empty()) {
-    if (hipEventCreateWithFlags(&t.ev, hipEventDisableTiming) != hipSuccess) {
-      t.ev = nullptr;
-      s->sticky = COG_E_DEVICE;
-      s->sticky_msg = "event creation failed";
-    }
-  } else {
-    t.ev = s->spare_events.back();
-    s->spare_events.pop_back();
-  }
+  t.ev = take_event(s);
   t.status = rc;
   if (t.ev && hipEventRecord(t.ev, s->stream) != hipSuccess) t.status = COG_E_DEVICE;
   s->in_flight.push_back(std::move(t));
@@ -250,9 +312,12 @@ bool issue_tick(cog_server *s) {
   return true;
 }
 
-// Completes the queued submissions of a failed server with its failure.
+// Completes the queued submissions of a failed server with its failure (and
+// drops the training still to issue).
 void fail_pending(cog_server *s) {
+  s->train_q.clear();
   for (auto &kv : s->streams) {
+    kv.second.training = false;
     while (!kv.second.q.empty()) {
       const Submission &sub = kv.second.q.front();
       cog_completion c{};
@@ -275,26 +340,36 @@ bool any_pending(const cog_server *s) {
   return false;
 }
 
-// Scheduler: issues a tick whenever something is queued and fewer than
-// depth ticks are in flight.
+// Scheduler: whenever fewer than depth ticks and slices are in flight, issues
+// a tick of what is queued or the next training slice, alternating between
+// the two while both wait.
 void scheduler_main(cog_server *s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
+  bool slice_next = false;
   while (true) {
     const bool pending = any_pending(s);
-    if (s->stop && !pending) break;
-    if (pending && s->sticky != COG_OK) {
+    const bool train = !s->train_q.empty();
+    if (s->stop && !pending && !train) break;
+    if ((pending || train) && s->sticky != COG_OK) {
       fail_pending(s);
       continue;
     }
-    if (pending && (int)s->in_flight.size() < s->depth) {
-      if (issue_tick(s)) {
+    if ((pending || train) && (int)s->in_flight.size() < s->depth) {
+      bool issued = false;
+      if (train && (slice_next || !pending)) issued = issue_slice(s);
+      if (!issued && pending) issued = issue_tick(s);
+      if (issued) {
+        slice_next = s->in_flight.back().slice_of < 0;
+      } else if (train) {
+        // everything queued waits for training
+        issued = issue_slice(s);
+        slice_next = false;
+      }
+      if (issued) {
         s->cv_flight.notify_one();
         continue;
       }
-      // everything queued waits for its stream's training: look again soon
-      s->cv_work.wait_for(lk, std::chrono::microseconds(100));
-      continue;
     }
     s->cv_work.wait(lk);
   }
@@ -328,10 +403,11 @@ void completer_main(cog_server *s) {
 bool idle(cog_server *s, int32_t id) {
   if (id >= 0) {
     auto it = s->streams.find(id);
-    return it == s->streams.end() || (it->second.q.empty() && it->second.in_flight == 0);
+    return it == s->streams.end() ||
+           (it->second.q.empty() && it->second.in_flight == 0 && !it->second.training);
   }
   for (auto &kv : s->streams)
-    if (!kv.second.q.empty() || kv.second.in_flight) return false;
+    if (!kv.second.q.empty() || kv.second.in_flight || kv.second.training) return false;
   return s->in_flight.empty();
 }
 
@@ -441,23 +517,16 @@ cog_status cog_server_open(cog_server *s, const cog_params *p, const void *train
     s->opening += 1;
   }
   // Built without the server lock, so ticks keep flowing: the context is
-  // created and trained on the side stream (the weight upload waits only for
-  // that stream), and its frames join ticks once the training event has
-  // completed.
+  // created on the side stream (the weight upload waits only for that
+  // stream); its training is issued by the scheduler in slices between ticks,
+  // and its frames join the first tick after the last slice.
   cog_ctx *ctx = nullptr;
-  hipEvent_t ev = nullptr;
-  rc = cog_create(p, s->train_stream, buf, bytes, &ctx);
-  if (rc == COG_OK) rc = cog_train_prior(ctx, train_frames, n_train, 1);
-  if (rc == COG_OK && (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-                       hipEventRecord(ev, s->train_stream) != hipSuccess)) {
-    rc = COG_E_DEVICE;
-    (void)hipStreamSynchronize(s->train_stream);
-  }
+  if (n_train < 2 || n_train > 65536) rc = sfail(COG_E_INVALID, "training needs 2 <= n <= 65536 frames");
+  else rc = cog_create(p, s->train_stream, buf, bytes, &ctx);
   std::lock_guard<std::mutex> lk(s->mu);
   s->opening -= 1;
   if (rc != COG_OK) {
     std::string msg = ctx ? cog_last_error(ctx) : cog_last_error(nullptr);
-    if (ev) (void)hipEventDestroy(ev);
     if (ctx) delete ctx;
     s->arena.give((size_t)(buf - s->arena.base), bytes);
     s->in_use -= bytes;
@@ -466,12 +535,17 @@ cog_status cog_server_open(cog_server *s, const cog_params *p, const void *train
   ctx->stream = s->stream;
   const int32_t nid = s->next_id++;
   SStream &st = s->streams[nid];
-  st.trained = ev;
   st.ctx = ctx;
   st.state = buf;
   st.bytes = bytes;
   st.pixels = (int64_t)p->width * p->height;
+  st.training = true;
+  st.train_frames = train_frames;
+  st.n_train = n_train;
+  st.train_next = 0;
+  s->train_q.push_back(nid);
   s->admitted += 1;
+  s->cv_work.notify_one();
   *id = nid;
   return COG_OK;
 }
@@ -497,8 +571,19 @@ cog_status cog_server_close(cog_server *s, int32_t id) {
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->streams.find(id);
   if (it == s->streams.end() || it->second.closing) return sfail(COG_E_INVALID, "no such open stream");
-  it->second.closing = true;
-  if (it->second.q.empty() && it->second.in_flight == 0) finalize(s, id);
+  SStream &st = it->second;
+  st.closing = true;
+  if (st.q.empty()) {
+    // nothing of the stream remains to run: the rest of its training is not
+    // needed, and once its slices in flight have ended (they are waited for
+    // here) its range returns at once
+    st.training = false;
+    if (st.in_flight == st.slices_in_flight) {
+      for (const Tick &t : s->in_flight)
+        if (t.slice_of == id && t.ev) (void)hipEventSynchronize(t.ev);
+      finalize(s, id);
+    }
+  }
   return COG_OK;
 }
 
@@ -523,12 +608,6 @@ cog_status cog_server_drain(cog_server *s, int32_t id) {
   s->cv_work.notify_one();
   s->cv_done.wait(lk, [s, id] { return idle(s, id) || s->sticky != COG_OK; });
   if (s->sticky != COG_OK) return sfail(s->sticky, "server failed: " + s->sticky_msg);
-  // a stream with nothing submitted may still be training
-  for (auto &kv : s->streams) {
-    if (id >= 0 && kv.first != id) continue;
-    if (!trained(kv.second) && hipEventSynchronize(kv.second.trained) != hipSuccess)
-      return sfail(COG_E_DEVICE, "training failed");
-  }
   return COG_OK;
 }
 
@@ -539,8 +618,6 @@ cog_status cog_server_export(cog_server *s, int32_t id, void *host_dst, size_t b
   if (s->sticky != COG_OK) return sfail(s->sticky, "server failed: " + s->sticky_msg);
   auto it = s->streams.find(id);
   if (it == s->streams.end()) return sfail(COG_E_INVALID, "no such open stream");
-  if (it->second.trained && hipEventSynchronize(it->second.trained) != hipSuccess)
-    return sfail(COG_E_DEVICE, "training failed");
   return cog_export_state(it->second.ctx, host_dst, bytes);
 }
 
