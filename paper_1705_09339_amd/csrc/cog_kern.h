@@ -620,89 +620,47 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
 // resident.
 constexpr int kTrainPx = 128;
 
-template <int C, int K, bool F32>
-__global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const void *frames,
-                                                        int64_t stride, int n, KParams kp,
-                                                        int64_t p0, int64_t p1) {
-  __shared__ uint4 s_w[256 * kBins * 2 / 16];
-  for (int i = threadIdx.x; i < 256 * kBins * 2 / 16; i += 2 * kTrainPx)
-    s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
-  __syncthreads();
-
-  const bool prior_role = threadIdx.x < kTrainPx;  // wave-uniform
-  const int t = prior_role ? threadIdx.x : threadIdx.x - kTrainPx;
-  const int lane = t & 63;
-  const int64_t p = p0 + (int64_t)blockIdx.x * kTrainPx + t;
-  const bool valid = p < p1;
-  if (prior_role) {
-    if (!valid) return;
-    uint32_t acc[C][kBins];
+// The prior record of a trained pixel from its bin masses acc and residue
+// counts: the max-normalised u8 table, the confidence weights and the counts.
+template <int C>
+__device__ __forceinline__ void store_prior(const Buffers &b, int64_t p,
+                                            const uint32_t (&acc)[C][kBins], uint32_t cnt0,
+                                            uint32_t cnt1, uint32_t cnt2, const KParams &kp) {
+  constexpr int PB = prior_bytes(C);
+  uint32_t words[PB / 4];
 #pragma unroll
-    for (int c = 0; c < C; ++c)
+  for (int i = 0; i < PB / 4; ++i) words[i] = 0u;
 #pragma unroll
-      for (int q = 0; q < kBins; ++q) acc[c][q] = 0u;
-    uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
-    float x[C], xp[C], xn[C];
-    load_px<C, F32>(frames, p, x);
-    if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
-    for (int j = 0; j < n; ++j) {
-      if (j >= 1) {
+  for (int c = 0; c < C; ++c) {
+    uint32_t amax = 0;
 #pragma unroll
-        for (int c = 0; c < C; ++c) x[c] = xn[c];
-        if (j + 1 < n) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
-      }
+    for (int q = 0; q < kBins; ++q) amax = acc[c][q] > amax ? acc[c][q] : amax;
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int v = quant<F32>(x[c], kp);
-        const uint4 lo = s_w[2 * v], hi = s_w[2 * v + 1];
-        const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          acc[c][2 * q] += wd[q] & 0xffffu;
-          acc[c][2 * q + 1] += wd[q] >> 16;
-        }
-      }
-      if (j >= 1) {
-        const float dl = frame_delta<C>(x, xp);
-        // residue bins [0, e1), [e1, e2), [e2, inf) counted without branches
-        const bool r0 = dl < kp.res_e1, r1 = !r0 && dl < kp.res_e2;
-        cnt0 += r0 ? 1u : 0u;
-        cnt1 += r1 ? 1u : 0u;
-        cnt2 += (!r0 && !r1) ? 1u : 0u;
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) xp[c] = x[c];
+    for (int q = 0; q < kBins; ++q) {
+      const uint32_t tq = amax ? round_ratio255(acc[c][q], amax) : 0u;
+      const int byte = c * kBins + q;
+      words[byte >> 2] |= (tq & 0xffu) << (8 * (byte & 3));
     }
-    constexpr int PB = prior_bytes(C);
-    uint32_t words[PB / 4];
-#pragma unroll
-    for (int i = 0; i < PB / 4; ++i) words[i] = 0u;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      uint32_t amax = 0;
-#pragma unroll
-      for (int q = 0; q < kBins; ++q) amax = acc[c][q] > amax ? acc[c][q] : amax;
-#pragma unroll
-      for (int q = 0; q < kBins; ++q) {
-        const uint32_t tq = amax ? round_ratio255(acc[c][q], amax) : 0u;
-        const int byte = c * kBins + q;
-        words[byte >> 2] |= (tq & 0xffu) << (8 * (byte & 3));
-      }
-    }
-    // confidence weights a, b, g = counts / (N - 1), divided once here
-    words[(C * kBins) / 4] = __float_as_uint((float)cnt0 / kp.nm1);
-    words[(C * kBins) / 4 + 1] = __float_as_uint((float)cnt1 / kp.nm1);
-    words[(C * kBins) / 4 + 2] = __float_as_uint((float)cnt2 / kp.nm1);
-    *reinterpret_cast<uint2 *>(b.cnt + p * 4) =
-        make_uint2((cnt0 & 0xffffu) | (cnt1 << 16), cnt2 & 0xffffu);
-    uint4 *dst = reinterpret_cast<uint4 *>(b.prior + p * PB);
-#pragma unroll
-    for (int i = 0; i < PB / 16; ++i)
-      dst[i] = make_uint4(words[4 * i], words[4 * i + 1], words[4 * i + 2], words[4 * i + 3]);
-    return;
   }
+  // confidence weights a, b, g = counts / (N - 1), divided once here
+  words[(C * kBins) / 4] = __float_as_uint((float)cnt0 / kp.nm1);
+  words[(C * kBins) / 4 + 1] = __float_as_uint((float)cnt1 / kp.nm1);
+  words[(C * kBins) / 4 + 2] = __float_as_uint((float)cnt2 / kp.nm1);
+  *reinterpret_cast<uint2 *>(b.cnt + p * 4) =
+      make_uint2((cnt0 & 0xffffu) | (cnt1 << 16), cnt2 & 0xffffu);
+  uint4 *dst = reinterpret_cast<uint4 *>(b.prior + p * PB);
+#pragma unroll
+  for (int i = 0; i < PB / 16; ++i)
+    dst[i] = make_uint4(words[4 * i], words[4 * i + 1], words[4 * i + 2], words[4 * i + 3]);
+}
 
-  // the mixture warm-up (initialised from frame 0, stepped on 1..N-1)
+// The mixture role of a training workgroup: the warm-up (initialised from
+// frame 0, stepped on 1..N-1) and the grouping sums of pixel p, then the
+// mixture record, running average, keys, previous value and label word.
+template <int C, int K, bool F32>
+__device__ __forceinline__ void train_mixture_role(const Buffers &b, const void *frames,
+                                                   int64_t stride, int n, const KParams &kp,
+                                                   int64_t p, bool valid, int lane) {
   bool lab = false;
   if (valid) {
     // grouping features: sums over the warm-up of the dominant component's
@@ -742,6 +700,65 @@ __global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const v
   const unsigned long long bal = __ballot(lab);
   const int64_t w0 = p - lane;
   if (lane == 0 && w0 < b.P) b.labels[w0 >> 6] = bal;
+}
+
+template <int C, int K, bool F32>
+__global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const void *frames,
+                                                        int64_t stride, int n, KParams kp,
+                                                        int64_t p0, int64_t p1) {
+  __shared__ uint4 s_w[256 * kBins * 2 / 16];
+  for (int i = threadIdx.x; i < 256 * kBins * 2 / 16; i += 2 * kTrainPx)
+    s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
+  __syncthreads();
+
+  const bool prior_role = threadIdx.x < kTrainPx;  // wave-uniform
+  const int t = prior_role ? threadIdx.x : threadIdx.x - kTrainPx;
+  const int lane = t & 63;
+  const int64_t p = p0 + (int64_t)blockIdx.x * kTrainPx + t;
+  const bool valid = p < p1;
+  if (!prior_role) {
+    train_mixture_role<C, K, F32>(b, frames, stride, n, kp, p, valid, lane);
+    return;
+  }
+  if (!valid) return;
+  uint32_t acc[C][kBins];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < kBins; ++q) acc[c][q] = 0u;
+  uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
+  float x[C], xp[C], xn[C];
+  load_px<C, F32>(frames, p, x);
+  if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
+  for (int j = 0; j < n; ++j) {
+    if (j >= 1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = xn[c];
+      if (j + 1 < n) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int v = quant<F32>(x[c], kp);
+      const uint4 lo = s_w[2 * v], hi = s_w[2 * v + 1];
+      const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        acc[c][2 * q] += wd[q] & 0xffffu;
+        acc[c][2 * q + 1] += wd[q] >> 16;
+      }
+    }
+    if (j >= 1) {
+      const float dl = frame_delta<C>(x, xp);
+      // residue bins [0, e1), [e1, e2), [e2, inf) counted without branches
+      const bool r0 = dl < kp.res_e1, r1 = !r0 && dl < kp.res_e2;
+      cnt0 += r0 ? 1u : 0u;
+      cnt1 += r1 ? 1u : 0u;
+      cnt2 += (!r0 && !r1) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) xp[c] = x[c];
+  }
+  store_prior<C>(b, p, acc, cnt0, cnt1, cnt2, kp);
 }
 
 // ============================================================================
