@@ -347,9 +347,11 @@ void cog_batch_destroy(cog_batch *b);
  * reserved once at creation and a stream is admitted only if its state fits
  * in a free range of it (ranges of closed streams are reused, neighbours
  * merged), so serving never allocates or frees device memory.  A new
- * stream trains on a side stream and its frames join ticks when that is
- * done.  Each stream's masks and state are bit-identical to the same frames
- * run alone through cog_step_frames.
+ * stream's training runs on the server's stream in slices of pixels that
+ * alternate with the ticks (a tick waits for at most one slice), and its
+ * frames join the first tick after the last slice.  Each stream's masks and
+ * state are bit-identical to the same frames run alone through
+ * cog_step_frames.
  *
  * Threading: every call may come from any thread; calls are serialised by
  * the server.  Frames and masks are device buffers owned by the caller and
@@ -391,12 +393,13 @@ cog_status cog_server_create(void *hip_stream, size_t hbm_budget, int32_t max_st
 /* Admit a stream: reserve its state within the budget, create its context
  * (parameters as for cog_create; cascade path, 64-pixel tiles) and run its
  * training on n_train device frames.  *id receives the stream's id.  The
- * training is enqueued on the server's side stream and the call returns
- * before it ends: train_frames must stay valid until the training has ended,
- * that is until the stream's first completion is reported or until
- * cog_server_drain of the stream (or of all streams) returns.
+ * training is issued later by the scheduler, in slices between ticks, and
+ * the call returns at once: train_frames must stay valid until the training
+ * has ended, that is until the stream's first completion is reported or
+ * until cog_server_drain of the stream (or of all streams) returns.
  * COG_E_OOM when the state does not fit the budget or max_streams streams
- * are open; other errors as for cog_create and cog_train_prior. */
+ * are open; COG_E_INVALID for n_train outside 2..65536; other errors as for
+ * cog_create and cog_train_prior. */
 cog_status cog_server_open(cog_server *s, const cog_params *p, const void *train_frames,
                            int32_t n_train, int32_t *id);
 
