@@ -1706,7 +1706,6 @@ __device__ __forceinline__ void frame_tile(const Buffers &b, const Frames &fr, c
   constexpr int R = rec_floats(C, K);
   constexpr int RG = rga_floats(C);
   constexpr int PB = prior_bytes(C);
-  constexpr int NXW = FrameLds<C, F32>::NXW;
   // input dwords of a lane's PX pixels (u8: PX*C bytes; f32: PX*C floats)
   constexpr int NDW = F32 ? PX * C : (PX * C) / 4;
   static_assert(F32 || (PX * C) % 4 == 0, "u8 lanes hold whole dwords");
