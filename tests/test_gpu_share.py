@@ -329,3 +329,54 @@ def test_shared_u8_single_channel_k2(C):
     p = gpu_params(C, 96, 64, c=1, K=2)
     say("share + u8 C=1 K=2")
     _share_run(C, p, fr, 30, 60)
+
+
+@pytest.mark.parametrize("mode", ["frames", "step"])
+def test_shared_value_held_at_var_min(C, mode):
+    """var_min = var_init = 12 + 2^-20, off the 2^-16 grid: after constant
+    training every variance is var_min, whose grid value is 12, so the fit
+    must hold the shared value at var_min.  A given map (group 0, group 2 and
+    ungrouped pixels, group 1 empty) over 910 pixels (ragged tiles); later
+    frames carry noise and an object, so the ungrouped pixels adapt."""
+    import torch
+    vm = 12.0 + 2.0 ** -20
+    H, W, N, T = 13, 70, 20, 44
+    rng = np.random.default_rng(170509346)
+    fr = synth.constant_stream(T, H, W, 3, [90, 100, 110])
+    fr[N:] = np.clip(fr[N:].astype(np.int16) + rng.integers(-6, 7, size=fr[N:].shape), 0,
+                     255).astype(np.uint8)
+    fr[N + 10:, 3:9, 20:41] = 200
+    p = gpu_params(C, W, H, K=3, var_min=vm, var_init=vm)
+    P = W * H
+    m = np.full(P, 255, dtype=np.uint8)
+    m[0::3] = 0
+    m[1::3] = 2
+    say("share at var_min, mode", mode)
+    dev = torch.from_numpy(np.ascontiguousarray(fr)).cuda()
+    s = C.CogStream(p, stream=torch.cuda.current_stream())
+    o = O.Oracle(orc_params_like(p))
+    try:
+        s.train_prior(dev[:N])
+        o.train(fr[:N])
+        gv, go = s.share(m), o.group_share(m)
+        assert np.array_equal(gv.view(np.uint32), go.view(np.uint32)), (gv, go)
+        assert gv[0] == np.float32(vm) and gv[1] == 0.0 and gv[2] == np.float32(vm)
+        _same_state(canon.parse(s.export_state()), canon.parse(o.export()))
+        masks = torch.zeros((T - N, P), dtype=torch.uint8, device="cuda")
+        if mode == "frames":
+            ig = s.step_frames(dev[N:], masks, want_info=True)
+        else:
+            ig = [s.step(dev[t], masks[t - N], want_info=True) for t in range(N, T)]
+        torch.cuda.synchronize()
+        mg = masks.cpu().numpy()
+        for t in range(N, T):
+            mo_t, io = o.step(fr[t])
+            assert np.array_equal(mg[t - N], mo_t), t
+            assert dict(ig[t - N]) == io, (t, dict(ig[t - N]), io)
+        st = canon.parse(s.export_state())
+        _same_state(st, canon.parse(o.export()))
+        assert (st["rga"][m != 255, -1] == np.float32(vm)).all()
+        assert (st["rga"][m == 255, -1] != np.float32(vm)).any()
+    finally:
+        s.close()
+        o.close()

@@ -5,7 +5,8 @@ the mean of the members' variances, and stop adapting it.
 
 The pins do not restate the formula.  They check what the mathematics fixes:
 the mean of identical values on the 2^-16 grid is that value, the mean lies
-within the grid's rounding of the float64 mean of the members, an empty map
+within the grid's rounding of the float64 mean of the members, it is never
+below var_min even where the grid rounds the members below it, an empty map
 changes nothing, pixels outside the groups evolve exactly as without
 grouping (pixels are independent), a shared variance never moves while the
 means still adapt, and ungrouping lets the variance adapt again."""
@@ -44,6 +45,21 @@ def test_identical_members_share_their_own_value():
     assert (_var(o) == v0[0]).all()
     st = canon.parse(o.export())
     assert st["version"] == 3 and (st["shared"] == 1).all()
+
+
+def test_shared_value_is_held_at_var_min():
+    """var_min off the 2^-16 grid (12 + 2^-20): constant input holds every
+    variance at var_min, whose grid value is 12, below var_min; the shared
+    value is var_min itself, never less."""
+    vm = 12.0 + 2.0 ** -20
+    assert float(np.float32(vm)) == vm and np.rint(vm * 65536.0) / 65536.0 == 12.0
+    fr = synth.constant_stream(30, 3, 4, 3, [90, 100, 110])
+    o = O.Oracle(O.make_params(4, 3, 3, 3, var_min=vm, var_init=vm))
+    o.train(fr)
+    assert (_var(o) == np.float32(vm)).all()
+    gv = o.group_share(np.zeros(12, dtype=np.uint8))
+    assert gv[0] == np.float32(vm)
+    assert (_var(o) == np.float32(vm)).all()
 
 
 def test_shared_value_is_the_members_mean():
