@@ -172,13 +172,12 @@ __device__ __forceinline__ void mix_step(Mix<C, K> &s, const float (&x)[C], floa
     for (int k = 0; k < K; ++k) s.w[k] = s.w[k] / S;
   }
 
-  // Re-rank by w/sigma: stable insertion sort.  If no adjacent pair is out of
-  // order the insertion sort exchanges nothing (every pass stops at its first
-  // comparison), so the exchange network runs only in lanes with an adjacent
-  // inversion.  The network itself is the insertion sort written as a fixed
-  // compare-exchange sequence: inside the already ranked prefix no pair ranks
-  // out of order (the key comparison is antisymmetric), so the extra
-  // comparisons never exchange and the result equals the early-exit sort.
+  // Re-rank by w/sigma: stable insertion sort with early exit, pass i moving
+  // slot i toward the front while it ranks strictly above its predecessor.
+  // If no adjacent pair is out of order no pass exchanges anything, so the
+  // passes run only in lanes with an adjacent inversion.  A lane stops a pass
+  // at its first comparison without exchange, exactly as the sequential sort;
+  // the wave leaves the pass once none of its lanes is still moving.
   int mp = m;
   bool inverted = false;
 #pragma unroll
@@ -187,11 +186,14 @@ __device__ __forceinline__ void mix_step(Mix<C, K> &s, const float (&x)[C], floa
   if (inverted) {
 #pragma unroll
     for (int i = 1; i < K; ++i) {
+      bool mv = true;
 #pragma unroll
       for (int j = i; j > 0; --j) {
         const float lhs = (s.w[j] * s.w[j]) * s.var[j - 1];
         const float rhs = (s.w[j - 1] * s.w[j - 1]) * s.var[j];
-        if (lhs > rhs) {
+        mv = mv && lhs > rhs;
+        if (__ballot(mv) == 0ull) break;
+        if (mv) {
           float t = s.w[j];
           s.w[j] = s.w[j - 1];
           s.w[j - 1] = t;
@@ -702,13 +704,33 @@ __device__ __forceinline__ void train_mixture_role(const Buffers &b, const void 
   if (lane == 0 && w0 < b.P) b.labels[w0 >> 6] = bal;
 }
 
+// Widened weights: the table holds each weight in 32 bits, so that one
+// 64-bit add accumulates two adjacent bins (neither half can carry:
+// n * 65535 < 2^32 for n <= 65536).  Used for u8 input with K <= 6, where
+// the mixture role leaves room for it at 7 waves per SIMD; f32 input (whose
+// quantisation needs registers) and larger mixtures keep the 16-bit table
+// and one add per bin.
+template <int K, bool F32>
+constexpr bool train_wide_table() { return !F32 && K <= 6; }
+// Minimum waves per SIMD asked of the compiler (1: no constraint).
+template <int K, bool F32>
+constexpr int train_prior_waves() { return train_wide_table<K, F32>() ? 7 : 1; }
+
 template <int C, int K, bool F32>
-__global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const void *frames,
-                                                        int64_t stride, int n, KParams kp,
-                                                        int64_t p0, int64_t p1) {
-  __shared__ uint4 s_w[256 * kBins * 2 / 16];
-  for (int i = threadIdx.x; i < 256 * kBins * 2 / 16; i += 2 * kTrainPx)
-    s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
+__global__ __launch_bounds__(2 * kTrainPx)
+__attribute__((amdgpu_waves_per_eu(train_prior_waves<K, F32>()))) void k_train_prior(
+    Buffers b, const void *frames, int64_t stride, int n, KParams kp, int64_t p0, int64_t p1) {
+  constexpr bool WIDE = train_wide_table<K, F32>();
+  constexpr int TW = WIDE ? 256 * kBins / 4 : 256 * kBins / 8;  // uint4 words
+  __shared__ uint4 s_w[TW];
+  for (int i = threadIdx.x; i < TW; i += 2 * kTrainPx) {
+    if constexpr (WIDE) {
+      const uint2 h = reinterpret_cast<const uint2 *>(b.kdew)[i];
+      s_w[i] = make_uint4(h.x & 0xffffu, h.x >> 16, h.y & 0xffffu, h.y >> 16);
+    } else {
+      s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
+    }
+  }
   __syncthreads();
 
   const bool prior_role = threadIdx.x < kTrainPx;  // wave-uniform
@@ -721,11 +743,16 @@ __global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const v
     return;
   }
   if (!valid) return;
+  // wide: bins 2q (low half) and 2q + 1 (high half) of acc2[c][q]
+  uint64_t acc2[C][WIDE ? kBins / 2 : 1];
   uint32_t acc[C][kBins];
 #pragma unroll
-  for (int c = 0; c < C; ++c)
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int q = 0; q < (WIDE ? kBins / 2 : 1); ++q) acc2[c][q] = 0u;
 #pragma unroll
     for (int q = 0; q < kBins; ++q) acc[c][q] = 0u;
+  }
   uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
   float x[C], xp[C], xn[C];
   load_px<C, F32>(frames, p, x);
@@ -739,12 +766,21 @@ __global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const v
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int v = quant<F32>(x[c], kp);
-      const uint4 lo = s_w[2 * v], hi = s_w[2 * v + 1];
-      const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      if constexpr (WIDE) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        acc[c][2 * q] += wd[q] & 0xffffu;
-        acc[c][2 * q + 1] += wd[q] >> 16;
+        for (int h = 0; h < kBins / 4; ++h) {
+          const uint4 w4 = s_w[(kBins / 4) * v + h];
+          acc2[c][2 * h] += (uint64_t)w4.x | ((uint64_t)w4.y << 32);
+          acc2[c][2 * h + 1] += (uint64_t)w4.z | ((uint64_t)w4.w << 32);
+        }
+      } else {
+        const uint4 lo = s_w[2 * v], hi = s_w[2 * v + 1];
+        const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          acc[c][2 * q] += wd[q] & 0xffffu;
+          acc[c][2 * q + 1] += wd[q] >> 16;
+        }
       }
     }
     if (j >= 1) {
@@ -757,6 +793,15 @@ __global__ __launch_bounds__(2 * kTrainPx) void k_train_prior(Buffers b, const v
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) xp[c] = x[c];
+  }
+  if constexpr (WIDE) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q = 0; q < kBins / 2; ++q) {
+        acc[c][2 * q] = (uint32_t)acc2[c][q];
+        acc[c][2 * q + 1] = (uint32_t)(acc2[c][q] >> 32);
+      }
   }
   store_prior<C>(b, p, acc, cnt0, cnt1, cnt2, kp);
 }
