@@ -84,11 +84,13 @@ __device__ __forceinline__ int mix_bgset(const Mix<C, K> &s, float T) {
 // component's mean and variance move with rho = a / w_m, an unmatched value
 // replaces the last-ranked slot, weights are renormalised and the slots are
 // re-ranked by w/sigma (stable).  Returns the label (1 = foreground) and the
-// matched slot's rank after the re-sort (-1 when nothing matched).
-template <int C, int K>
+// matched slot's rank after the re-sort (-1 when nothing matched).  LABEL
+// false skips the background set and returns label 0, for warm-up frames
+// whose label is not kept; the state update is the same.
+template <int C, int K, bool LABEL = true>
 __device__ __forceinline__ void mix_step(Mix<C, K> &s, const float (&x)[C], float ae,
                                          const KParams &kp, int &label, int &mpost) {
-  const int B = mix_bgset<C, K>(s, kp.T);
+  const int B = LABEL ? mix_bgset<C, K>(s, kp.T) : K;
   // first matching rank: every distance is evaluated (no short-circuit) and
   // the scan runs from the last rank down, so the lowest hit wins as a select
   int m = -1;
@@ -103,7 +105,7 @@ __device__ __forceinline__ void mix_step(Mix<C, K> &s, const float (&x)[C], floa
     const bool hit = (s.w[k] > 0.0f) & (d2 <= kp.lam2 * s.var[k]);
     m = hit ? k : m;
   }
-  label = (m >= 0 && m < B) ? 0 : 1;
+  label = LABEL ? ((m >= 0 && m < B) ? 0 : 1) : 0;
 
   const float om = 1.0f - ae;
 #pragma unroll
@@ -589,16 +591,26 @@ __global__ __launch_bounds__(kNT) void k_train(Buffers b, const void *frames, in
     mix_init<C, K>(m, x, kp.var_init);
     // the next frame's value is requested one frame ahead, so its latency
     // overlaps the current frame's work
-    if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
-    for (int j = 0; j < n; ++j) {
-      if (j >= 1) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) x[c] = xn[c];
-        if (j + 1 < n) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
-        int l, mp;
-        mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
-        lab = l != 0;
-      }
+    for (int c = 0; c < C; ++c) xp[c] = x[c];
+    if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
+    // frames 1..n-2 without the label (only the last frame's is kept), then
+    // frame n-1 with it
+    for (int j = 1; j + 1 < n; ++j) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = xn[c];
+      load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
+      int l, mp;
+      mix_step<C, K, false>(m, x, kp.alpha, kp, l, mp);
+#pragma unroll
+      for (int c = 0; c < C; ++c) xp[c] = x[c];
+    }
+    if (n > 1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = xn[c];
+      int l, mp;
+      mix_step<C, K, true>(m, x, kp.alpha, kp, l, mp);
+      lab = l != 0;
 #pragma unroll
       for (int c = 0; c < C; ++c) xp[c] = x[c];
     }
@@ -672,20 +684,34 @@ __device__ __forceinline__ void train_mixture_role(const Buffers &b, const void 
     Mix<C, K> m;
     load_px<C, F32>(frames, p, x);
     mix_init<C, K>(m, x, kp.var_init);
-    if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
-    for (int j = 0; j < n; ++j) {
-      if (j >= 1) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) x[c] = xn[c];
-        if (j + 1 < n) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
-        int l, mp;
-        mix_step<C, K>(m, x, kp.alpha, kp, l, mp);
-        lab = l != 0;
-        sv = sv + m.var[0];
-        qv = qv + m.var[0] * m.var[0];
-        sw = sw + m.w[0];
-        qw = qw + m.w[0] * m.w[0];
-      }
+    for (int c = 0; c < C; ++c) xp[c] = x[c];
+    if (n > 1) load_px<C, F32>(frame_ptr<C, F32>(frames, stride, 1), p, xn);
+    // frames 1..n-2 without the label (only the last frame's is kept), then
+    // frame n-1 with it
+    for (int j = 1; j + 1 < n; ++j) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = xn[c];
+      load_px<C, F32>(frame_ptr<C, F32>(frames, stride, j + 1), p, xn);
+      int l, mp;
+      mix_step<C, K, false>(m, x, kp.alpha, kp, l, mp);
+      sv = sv + m.var[0];
+      qv = qv + m.var[0] * m.var[0];
+      sw = sw + m.w[0];
+      qw = qw + m.w[0] * m.w[0];
+#pragma unroll
+      for (int c = 0; c < C; ++c) xp[c] = x[c];
+    }
+    if (n > 1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[c] = xn[c];
+      int l, mp;
+      mix_step<C, K, true>(m, x, kp.alpha, kp, l, mp);
+      lab = l != 0;
+      sv = sv + m.var[0];
+      qv = qv + m.var[0] * m.var[0];
+      sw = sw + m.w[0];
+      qw = qw + m.w[0] * m.w[0];
 #pragma unroll
       for (int c = 0; c < C; ++c) xp[c] = x[c];
     }
@@ -706,12 +732,12 @@ __device__ __forceinline__ void train_mixture_role(const Buffers &b, const void 
 
 // Widened weights: the table holds each weight in 32 bits, so that one
 // 64-bit add accumulates two adjacent bins (neither half can carry:
-// n * 65535 < 2^32 for n <= 65536).  Used for u8 input with K <= 6, where
+// n * 65535 < 2^32 for n <= 65536).  Used for u8 input with K <= 7, where
 // the mixture role leaves room for it at 7 waves per SIMD; f32 input (whose
-// quantisation needs registers) and larger mixtures keep the 16-bit table
-// and one add per bin.
+// quantisation needs registers) and K = 8 keep the 16-bit table and one add
+// per bin.
 template <int K, bool F32>
-constexpr bool train_wide_table() { return !F32 && K <= 6; }
+constexpr bool train_wide_table() { return !F32 && K <= 7; }
 // Minimum waves per SIMD asked of the compiler (1: no constraint).
 template <int K, bool F32>
 constexpr int train_prior_waves() { return train_wide_table<K, F32>() ? 7 : 1; }
