@@ -1,7 +1,8 @@
 """Edge cases of the HIP path against the oracle, bit for bit: each cascade
 stage alone and in pairs, frames smaller than a tile or one pixel wide or
 tall, parameter extremes, and a run long enough for mixture weights to decay
-into binary32 subnormals (the build keeps IEEE denormals on both sides)."""
+into binary32 subnormals (the build keeps IEEE denormals on both sides), and
+the shortest and longest training the library accepts."""
 import numpy as np
 import pytest
 
@@ -112,3 +113,33 @@ def test_subnormal_weights_long_run(C):
     w = so["gmm"][..., 0]
     sub = (w > 0) & (w < np.finfo(np.float32).tiny)
     assert sub.any(), "no weight reached the subnormal range"
+
+
+@pytest.mark.parametrize("n_train", [2, 65536], ids=["shortest", "longest"])
+def test_training_length_extremes(C, n_train):
+    """The shortest and longest training the library accepts (2 and 65 536
+    frames) on a 16x8 frame whose channels sit near the centres of prior bins
+    0, 1 and 12 with small noise.  At 65 536 frames the bin masses of an even
+    and an odd bin pass 2^31, the residue counts reach 65 535, and the u8
+    path's paired 32-bit accumulators come closest to their limit; the prior
+    table, counts, mixture and every later frame stay bitwise equal."""
+    rng = np.random.default_rng(170509347)
+    H, W, extra = 8, 16, 8
+    T = n_train + extra
+    centre = np.array([8, 24, 200], dtype=np.int16)
+    fr = np.empty((T, H, W, 3), dtype=np.uint8)
+    for t0 in range(0, T, 4096):
+        t1 = min(T, t0 + 4096)
+        noise = rng.integers(-2, 3, size=(t1 - t0, H, W, 3), dtype=np.int16)
+        fr[t0:t1] = np.clip(centre + noise, 0, 255).astype(np.uint8)
+    fr[n_train:, 2:5, 3:9] = [250, 10, 90]
+    say("training length", n_train)
+    p = gpu_params(C, W, H, K=3)
+    mg, ig, sg = run_gpu(C, p, fr, n_train, mode="step")
+    mo, io, so = run_orc(orc_params_like(p), fr, n_train)
+    assert np.array_equal(mg, mo)
+    compare_infos(ig, io)
+    assert compare_state(sg, so, keys=KEYS + ("gkey",)) == 0
+    assert sum(i["n_fg"] for i in io) > 0
+    if n_train == 65536:
+        assert int(so["cnt"].max()) == 65535
