@@ -370,6 +370,11 @@ void scheduler_main(cog_server *s) {
         s->cv_flight.notify_one();
         continue;
       }
+      // nothing issued because the training queue held only streams closed
+      // before their slices ran, which issue_slice has dropped: test the
+      // loop's conditions again, since a stop may already be waiting and no
+      // completion would wake this thread
+      if (train && s->train_q.empty()) continue;
     }
     s->cv_work.wait(lk);
   }

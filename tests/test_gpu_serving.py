@@ -163,6 +163,30 @@ def test_admission_by_budget_and_pool_reuse(C):
     srv.close()
 
 
+def test_close_before_training_then_destroy(C):
+    """Streams closed right after admission, before the scheduler has issued
+    their training slices, leave stale entries in the training queue; the
+    server must still shut down.  Each round opens a stream needing several
+    slices and one needing one, closes both at once, checks that nothing
+    remains open and destroys the server."""
+    import torch
+    big = torch.zeros((20, 600, 1024, 3), dtype=torch.uint8, device="cuda")  # 3 slices
+    small = torch.from_numpy(_synth(16, 8, 20, 9)).cuda()
+    torch.cuda.synchronize()
+    pb = gpu_params(C, 1024, 600, c=3, K=3)
+    ps = gpu_params(C, 16, 8, c=3, K=3)
+    for r in range(8):
+        say("close before training, round", r)
+        srv = C.CogServer(hbm_budget=2 * C.cog_state_bytes(pb), max_streams=4)
+        a = srv.open(pb, big)
+        b = srv.open(ps, small)
+        srv.close_stream(b)
+        srv.close_stream(a)
+        st = srv.stats()
+        assert st["streams_open"] == 0 and st["bytes_in_use"] == 0
+        srv.close()
+
+
 def test_close_with_pending_frames_and_errors(C):
     import torch
     fr = torch.from_numpy(_synth(24, 16, 40, 6)).cuda()
