@@ -749,12 +749,16 @@ __attribute__((amdgpu_waves_per_eu(train_prior_waves<K, F32>()))) void k_train_p
   constexpr bool WIDE = train_wide_table<K, F32>();
   constexpr int TW = WIDE ? 256 * kBins / 4 : 256 * kBins / 8;  // uint4 words
   __shared__ uint4 s_w[TW];
+  // chunk-major in LDS: chunk h of level v at s_w[h * 256 + v], so lanes whose
+  // levels lie within a few steps of each other read different banks
+  constexpr int NCH = TW / 256;  // 16-byte chunks per level
   for (int i = threadIdx.x; i < TW; i += 2 * kTrainPx) {
+    const int v = i / NCH, h = i % NCH;
     if constexpr (WIDE) {
-      const uint2 h = reinterpret_cast<const uint2 *>(b.kdew)[i];
-      s_w[i] = make_uint4(h.x & 0xffffu, h.x >> 16, h.y & 0xffffu, h.y >> 16);
+      const uint2 w = reinterpret_cast<const uint2 *>(b.kdew)[i];
+      s_w[h * 256 + v] = make_uint4(w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16);
     } else {
-      s_w[i] = reinterpret_cast<const uint4 *>(b.kdew)[i];
+      s_w[h * 256 + v] = reinterpret_cast<const uint4 *>(b.kdew)[i];
     }
   }
   __syncthreads();
@@ -795,12 +799,12 @@ __attribute__((amdgpu_waves_per_eu(train_prior_waves<K, F32>()))) void k_train_p
       if constexpr (WIDE) {
 #pragma unroll
         for (int h = 0; h < kBins / 4; ++h) {
-          const uint4 w4 = s_w[(kBins / 4) * v + h];
+          const uint4 w4 = s_w[h * 256 + v];
           acc2[c][2 * h] += (uint64_t)w4.x | ((uint64_t)w4.y << 32);
           acc2[c][2 * h + 1] += (uint64_t)w4.z | ((uint64_t)w4.w << 32);
         }
       } else {
-        const uint4 lo = s_w[2 * v], hi = s_w[2 * v + 1];
+        const uint4 lo = s_w[v], hi = s_w[256 + v];
         const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
