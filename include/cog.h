@@ -410,9 +410,11 @@ cog_status cog_server_open(cog_server *s, const cog_params *p, const void *train
 cog_status cog_server_submit(cog_server *s, int32_t id, const void *frames, int32_t nframes,
                              uint8_t *masks, int64_t tag);
 
-/* Close stream id: its queued frames still complete; then its state range
- * returns to the reservation (after the stream's training, if that is still
- * running).  COG_E_INVALID for an unknown id. */
+/* Close stream id.  Its queued frames still complete, after the rest of its
+ * training, and then its state range returns to the reservation.  With
+ * nothing queued, the training slices not yet issued are dropped; the call
+ * waits for those in flight and returns the range at once.  COG_E_INVALID
+ * for an unknown or already closing id. */
 cog_status cog_server_close(cog_server *s, int32_t id);
 
 /* Move up to max completions (oldest first) to out; *n receives the count.
